@@ -1,0 +1,243 @@
+"""Plain FP64 CPU oracle for grid-refined KBC lattice Boltzmann (ctypes binding).
+
+TEST INFRASTRUCTURE: the independent reference for the HIP library.  Only the test
+suite, the smoke check and the benchmark's CPU-baseline leg may import this package.
+The arithmetic lives in ``elbm_oracle.c``; this module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "elbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FACE_WALL, FACE_INLET, FACE_OUTFLOW = 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE arithmetic)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_create.restype = P
+        L.ora_create.argtypes = [ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int]
+        L.ora_destroy.argtypes = [P]
+        L.ora_error.restype = ctypes.c_char_p
+        L.ora_error.argtypes = [P]
+        for name, args in [
+            ("ora_set_face", [P, ctypes.c_int, ctypes.c_int, dp]),
+            ("ora_add_box", [P, ctypes.c_int, i64p, i64p]),
+            ("ora_set_solid", [P, ctypes.c_int, i64p, i64p, ctypes.c_void_p]),
+            ("ora_set_force_uniform", [P, dp]),
+            ("ora_finalize", [P]),
+            ("ora_level_box", [P, ctypes.c_int, i64p, i64p]),
+            ("ora_level_info", [P, ctypes.c_int, i64p, i64p, dp]),
+            ("ora_node_class", [P, ctypes.c_int, ctypes.c_void_p]),
+            ("ora_weights", [P, ctypes.c_int, dp]),
+            ("ora_init", [P, ctypes.c_int, dp, dp, dp]),
+            ("ora_set_force_field", [P, ctypes.c_int, dp]),
+            ("ora_set_f", [P, ctypes.c_int, dp]),
+            ("ora_advance", [P, ctypes.c_int]),
+            ("ora_get_f", [P, ctypes.c_int, dp]),
+            ("ora_moments", [P, ctypes.c_int, dp, dp, dp]),
+            ("ora_sample_f", [P, ctypes.c_int, ctypes.c_int64, i64p, dp]),
+            ("ora_reduce", [P, dp, dp]),
+            ("ora_drag", [P, ctypes.c_int, dp, i64p, ctypes.c_int]),
+        ]:
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = args
+        L.ora_feq.restype = None
+        L.ora_feq.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.ora_kbc.restype = ctypes.c_double
+        L.ora_kbc.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
+        L.ora_beta.restype = ctypes.c_double
+        L.ora_beta.argtypes = [ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i64(v):
+    a = np.zeros(3, dtype=np.int64)
+    a[: len(v)] = v
+    return a
+
+
+def _f3(v):
+    a = np.zeros(3, dtype=np.float64)
+    a[: len(v)] = v
+    return a
+
+
+def q_of(D: int) -> int:
+    return 9 if D == 2 else 27
+
+
+def beta(nu: float) -> float:
+    return lib().ora_beta(float(nu))
+
+
+def feq(D: int, rho: float, u) -> np.ndarray:
+    out = np.empty(q_of(D))
+    uu = _f3(u)
+    lib().ora_feq(D, float(rho), _dp(uu), _dp(out))
+    return out
+
+
+def kbc(D: int, beta_: float, f, F=(0.0, 0.0, 0.0)):
+    """One collision; returns (f_post, gamma, ds, dh)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    Q = q_of(D)
+    out, ds, dh = np.empty(Q), np.empty(Q), np.empty(Q)
+    FF = _f3(F)
+    g = lib().ora_kbc(D, float(beta_), _dp(f), _dp(FF), _dp(out), _dp(ds), _dp(dh))
+    return out, g, ds, dh
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """The refined KBC hierarchy, run literally on the CPU in FP64."""
+
+    def __init__(self, D, N, periodic, nu0, n_levels):
+        self.D, self.Q, self.L = D, q_of(D), n_levels
+        per = (ctypes.c_int * 3)(*[int(bool(p)) for p in list(periodic) + [0] * (3 - len(periodic))])
+        NN = _i64(N)
+        self._h = lib().ora_create(D, NN.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), per, float(nu0), n_levels)
+        if not self._h:
+            raise OracleError("ora_create failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().ora_destroy(h)
+            self._h = None
+
+    def _ck(self, rc):
+        if rc != 0:
+            raise OracleError("oracle error %d: %s" % (rc, lib().ora_error(self._h).decode()))
+
+    @staticmethod
+    def _p64(a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def set_face(self, face, kind, u=(0.0, 0.0, 0.0)):
+        uu = _f3(u)
+        self._ck(lib().ora_set_face(self._h, face, kind, _dp(uu)))
+
+    def add_box(self, level, lo, hi):
+        a, b = _i64(lo), _i64(hi)
+        self._ck(lib().ora_add_box(self._h, level, self._p64(a), self._p64(b)))
+
+    def set_solid(self, level, lo, mask):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        n = list(mask.shape[::-1]) + [1] * (3 - mask.ndim)
+        a, b = _i64(lo), _i64(n)
+        self._ck(lib().ora_set_solid(self._h, level, self._p64(a), self._p64(b), mask.ctypes.data))
+
+    def set_force_uniform(self, F):
+        FF = _f3(F)
+        self._ck(lib().ora_set_force_uniform(self._h, _dp(FF)))
+
+    def finalize(self):
+        self._ck(lib().ora_finalize(self._h))
+
+    def level_box(self, level):
+        lo, n = np.zeros(3, np.int64), np.zeros(3, np.int64)
+        self._ck(lib().ora_level_box(self._h, level, self._p64(lo), self._p64(n)))
+        return lo, n
+
+    def shape(self, level):
+        """numpy shape of a dense level array (z, y, x) or (y, x)."""
+        _, n = self.level_box(level)
+        return tuple(int(v) for v in n[: self.D][::-1])
+
+    def level_info(self, level):
+        nn, nf = ctypes.c_int64(), ctypes.c_int64()
+        b = ctypes.c_double()
+        self._ck(lib().ora_level_info(self._h, level, ctypes.byref(nn), ctypes.byref(nf), ctypes.byref(b)))
+        return nn.value, nf.value, b.value
+
+    def node_class(self, level):
+        out = np.empty(self.shape(level), dtype=np.int32)
+        self._ck(lib().ora_node_class(self._h, level, out.ctypes.data))
+        return out
+
+    def weights(self, level):
+        out = np.empty(self.shape(level))
+        self._ck(lib().ora_weights(self._h, level, _dp(out)))
+        return out
+
+    def init(self, level, rho, u, noise=None):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+        self._ck(lib().ora_init(self._h, level, _dp(rho), _dp(u), None if nz is None else _dp(nz)))
+
+    def set_force_field(self, level, F):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        self._ck(lib().ora_set_force_field(self._h, level, _dp(F)))
+
+    def set_f(self, level, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._ck(lib().ora_set_f(self._h, level, _dp(f)))
+
+    def advance(self, n=1):
+        self._ck(lib().ora_advance(self._h, int(n)))
+
+    def get_f(self, level):
+        out = np.empty((self.Q,) + self.shape(level))
+        self._ck(lib().ora_get_f(self._h, level, _dp(out)))
+        return out
+
+    def moments(self, level):
+        sh = self.shape(level)
+        rho, u, g = np.empty(sh), np.empty((self.D,) + sh), np.empty(sh)
+        self._ck(lib().ora_moments(self._h, level, _dp(rho), _dp(u), _dp(g)))
+        return rho, u, g
+
+    def sample_f(self, level, coords):
+        c = np.zeros((len(coords), 3), dtype=np.int64)
+        c[:, : np.asarray(coords).shape[1]] = coords
+        out = np.empty((len(coords), self.Q))
+        self._ck(lib().ora_sample_f(self._h, level, len(coords), self._p64(c), _dp(out)))
+        return out
+
+    def reduce(self):
+        m = ctypes.c_double()
+        mom = np.zeros(3)
+        self._ck(lib().ora_reduce(self._h, ctypes.byref(m), _dp(mom)))
+        return m.value, mom[: self.D]
+
+    def drag(self, level, reset=False):
+        F = np.zeros(3)
+        st = ctypes.c_int64()
+        self._ck(lib().ora_drag(self._h, level, _dp(F), ctypes.byref(st), int(reset)))
+        return F[: self.D], st.value
