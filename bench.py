@@ -1,0 +1,226 @@
+"""Throughput of the refined KBC hot path on one MI355X.
+
+Workload (default): D3Q27 KBC two-level channel -- 128x64x64 coarse nodes, periodic
+x/z, bounce-back walls in y, refined near-wall slabs 8 coarse rows deep, constant
+body force for Re_tau ~ 180, seeded 5% velocity perturbations; FP32 populations.
+One step = one coarse step of the whole refined path (two fine substeps, interface
+gather/reconstruction/coalescence, every collision), replayed as one HIP graph.
+
+Metric: fine-equivalent MLUPS = sum_l N_l 2^l x coarse steps / s / 1e6 (N_l: fluid
+nodes of level l), i.e. the paper's time-step-weighted "equivalent fine level
+points" per second.  Also reported: the same for weight-shifted FP16 storage, the
+dominant kernel's roofline (stream-collide, HBM bound) and the FP64 CPU oracle on
+the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "fine-equiv MLUPS & HBM % (FP32 vs FP16 store); adjoint/forward time ratio"
+STORE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+
+
+def workload(name):
+    from paper_1608_06915_amd import synth
+
+    if name == "channel3d":
+        return synth.channel3d(), ("D3Q27 KBC two-level channel 128x64x64 coarse, periodic x/z, bounce-back y, "
+                                   "refined near-wall slabs 8 coarse rows, body force Re_tau~180, 5% seeded "
+                                   "velocity perturbations")
+    if name == "sphere3d":
+        return synth.sphere3d(), ("D3Q27 KBC flow past a sphere, 3 nested 2x levels, coarse 256x128x128, D=20 "
+                                  "finest units, inlet u=0.05, outflow, Re=300")
+    if name == "forest3d":
+        return synth.forest3d(), ("D3Q27 KBC periodic block forest, 4 levels, 512 blocks of 16^3 cells "
+                                  "(204/154/106/48), 2:1 balanced, seeded |u|<=0.05")
+    if name == "tgv2d":
+        return synth.tgv2d(), "D2Q9 KBC two-level Taylor-Green 64x64 coarse, refined [16,48]^2"
+    if name == "cylinder2d":
+        return synth.cylinder2d(), "D2Q9 KBC two-level channel 256x128 with cylinder D=32 fine, Re=100"
+    raise SystemExit("unknown workload " + name)
+
+
+def mode_counts(lat, sp):
+    """Nodes stream-collided per level and substep kind, from the node classes:
+    returns per level (first-substep count, every-step count)."""
+    out = []
+    for l in range(sp.levels):
+        c = lat.node_class(l)
+        fluid = (c >= 0) & ((c & 1) == 0)
+        ring = (c & 2) != 0
+        pd = (c >> 2) & 3
+        bulk = fluid & ~ring & ((pd >= 2) | (l == 0))
+        inner = fluid & ~ring & (pd == 1) & (l > 0)
+        out.append((int(bulk.sum() + inner.sum()), int(bulk.sum())))
+    return out
+
+
+def sc_bytes_per_coarse_step(sp, counts, sbytes):
+    """Algorithmic bytes of the stream-collide launches in one coarse step: each
+    processed node reads Q and writes Q populations."""
+    L = sp.levels
+    T = 1 << (L - 1)
+    per_node = 2 * sp.Q * sbytes
+    total_nodes, launches = 0, 0
+    for t in range(1, T + 1):
+        lmin = min(l for l in range(L) if t % (1 << (L - 1 - l)) == 0)
+        for l in range(lmin, L):
+            first = l == lmin and l > 0
+            total_nodes += counts[l][0] if first else counts[l][1]
+        launches += 1
+    return total_nodes * per_node, launches, total_nodes
+
+
+def fine_equiv_updates(lat, sp):
+    return sum(lat.level_info(l)[1] * (1 << l) for l in range(sp.levels))
+
+
+def run_gpu(sp, storage, steps, warmup, tune):
+    import torch
+
+    from paper_1608_06915_amd import elbm
+
+    lat = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    from paper_1608_06915_amd import synth
+
+    synth.apply(sp, lat)
+    lat.bind()
+    for l in range(sp.levels):
+        lo, n = lat.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        lat.init(l, rho, u, nz)
+    if tune:
+        lat.tune(os.environ.get("ELBM_TUNE_CACHE"), steps=3)
+    lat.advance(warmup)
+    lat.synchronize()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.advance(steps)
+    end.record(lat.stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    # the same number of steps again with HIP events around every stream-collide
+    # launch, on the stream the kernels are launched on
+    tot_ms, sc_ms, n_launch = lat.profile(steps)
+    ok = lat.check()
+    return lat, ms, sc_ms, n_launch, tot_ms, ok
+
+
+def cpu_baseline(sp, fe_updates, steps):
+    import oracle
+
+    t0 = time.time()
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
+    from paper_1608_06915_amd import synth
+
+    synth.apply(sp, o)
+    for l in range(sp.levels):
+        lo, n = o.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        o.init(l, rho, u, nz)
+    setup = time.time() - t0
+    t0 = time.time()
+    o.advance(steps)
+    dt = time.time() - t0
+    return fe_updates * steps / dt / 1e6, dt, setup
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--workload", default="channel3d")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-half", action="store_true")
+    ap.add_argument("--tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    sp, desc = workload(args.workload)
+    print("bench: workload=%s storage=%s steps=%d warmup=%d" % (args.workload, args.storage, args.steps,
+                                                                args.warmup), file=sys.stderr, flush=True)
+    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, args.tune)
+    fe = fine_equiv_updates(lat, sp)
+    value = fe * args.steps / (ms / 1e3) / 1e6
+    counts = mode_counts(lat, sp)
+    sbytes = STORE_BYTES[args.storage]
+    bytes_step, launches_step, nodes_step = sc_bytes_per_coarse_step(sp, counts, sbytes)
+    per_launch_bytes = bytes_step / launches_step
+    avg_launch_ms = sc_ms / max(n_launch, 1)
+    achieved = per_launch_bytes / (avg_launch_ms / 1e3) / 1e9
+    # whole-step HBM fraction with algorithmic bytes (every fluid node of every level
+    # reads and writes Q populations per level step)
+    step_bytes = fe * 2 * sp.Q * sbytes
+    hbm_pct = step_bytes / (ms / args.steps / 1e3) / 1e9 / PEAK_HBM_GBS * 100
+    print("bench: %s %.1f MLUPS_fe, %.3f ms/step, stream-collide %.3f ms/launch %.0f GB/s, stable=%s" % (
+        args.storage, value, ms / args.steps, avg_launch_ms, achieved, ok), file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "MLUPS (fine-equivalent)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": desc, "levels": sp.levels,
+                   "fluid_nodes_per_level": [lat.level_info(l)[1] for l in range(sp.levels)],
+                   "fine_equiv_updates_per_step": fe, "storage": args.storage, "compute": "f32" if
+                   args.storage != "f64" else "f64", "graph": True},
+        "hbm_pct_alg": round(hbm_pct, 2),
+        "stable": ok,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_stream_collide", "bytes_per_launch": int(per_launch_bytes),
+                     "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
+                     "bytes_per_node_update": 2 * sp.Q * sbytes},
+    }
+    if not args.no_half and args.storage == "f32":
+        lat2, ms2, sc2, nl2, _, ok2 = run_gpu(sp, "f16s", args.steps, args.warmup, args.tune)
+        v2 = fe * args.steps / (ms2 / 1e3) / 1e6
+        b2, l2, _ = sc_bytes_per_coarse_step(sp, counts, 2)
+        a2 = (b2 / l2) / (sc2 / max(nl2, 1) / 1e3) / 1e9
+        out["f16s"] = {"value": round(v2, 2), "ms_per_step": round(ms2 / args.steps, 5),
+                       "hbm_pct_alg": round(fe * 2 * sp.Q * 2 / (ms2 / args.steps / 1e3) / 1e9 / PEAK_HBM_GBS * 100, 2),
+                       "stream_collide_GBs": round(a2, 1), "stable": ok2}
+        print("bench: f16s %.1f MLUPS_fe" % v2, file=sys.stderr, flush=True)
+        del lat2
+    if not args.no_cpu:
+        mlups, dt, setup = cpu_baseline(sp, fe, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(mlups, 4), "unit": "MLUPS (fine-equivalent)", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d coarse steps of the same workload, FP64 oracle, single thread "
+                                         "(%.1f s, setup %.1f s)" % (args.cpu_steps, dt, setup)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

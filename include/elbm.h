@@ -1,0 +1,195 @@
+/*
+ * elbm.h -- C ABI of the MI355X grid-refined entropic lattice Boltzmann library.
+ *
+ * Method: Dorschner, Frapolli, Chikatamarla, Karlin, "Grid refinement for entropic
+ * lattice Boltzmann models" (arXiv:1608.06915).  Per level, the KBC stream-collide of
+ * Sec. II.A (Eq. f_equations with the mirror state Eq. f_mirr, the product-form
+ * equilibrium Eq. feq_iso and the entropic stabiliser Eq. gamma_min_approx); between
+ * levels, the multi-domain coupling of Sec. III (non-equilibrium rescaling
+ * Eq. f_neq_rescaling_iso at twin nodes, four-point reconstruction Eq. interp at
+ * hanging nodes) and the five-step algorithm of Sec. III.C with two fine substeps per
+ * coarse step and no time interpolation, applied recursively over any number of
+ * levels with refinement ratio r = 2.
+ *
+ * Conventions
+ *   - Status: every call returns elbm_status; no exception or exit crosses the ABI.
+ *     On failure elbm_last_error(ctx) holds a message.
+ *   - Lattices: D2Q9 (dim 2) and D3Q27 (dim 3).  Velocity index
+ *     i = (cx+1) + 3(cy+1) [+ 9(cz+1)]; the opposite of i is Q-1-i.
+ *   - Units: lattice units of level 0 (the coarsest) at the boundary.  Level l has
+ *     spacing and time step 2^-l of level 0; its viscosity is 2^l nu0 (convective
+ *     scaling, Sec. III.A); body forces are force densities in level-0 units.
+ *   - Coordinates: level-l node coordinates are integers in level-l spacing.  A
+ *     periodic axis with N coarse nodes has period N 2^l at level l; a non-periodic
+ *     axis has nodes 0 .. (N-1) 2^l and its faces carry walls (default), an inlet or an
+ *     outflow.  Walls sit half a spacing of the level that resolves them outside
+ *     the last node (halfway bounce-back).
+ *   - Level index box: level 0 covers the domain; level l > 0 covers, per axis, the
+ *     hull of its blocks, or the whole period when a block spans or wraps it.  Dense
+ *     per-level arrays (fields, masks) cover that box, x fastest; vector fields are
+ *     [component][box]; population arrays are [Q][box].
+ *   - Memory: "_host" pointers are host memory, "_dev" pointers device memory.  The
+ *     caller owns both; the library keeps no caller pointer after a call returns,
+ *     except the bound workspace and stream.
+ *   - Threading: one context per stream; a context is not thread-safe.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ELBM_OK = 0,
+  ELBM_EINVAL = 1,    /* bad argument or geometry (not nested, misaligned, missing margin) */
+  ELBM_ESTATE = 2,    /* call out of order (e.g. advance before bind) */
+  ELBM_ESMALL = 3,    /* workspace smaller than elbm_finalize reported */
+  ELBM_EDEVICE = 4,   /* HIP runtime error; message in elbm_last_error */
+  ELBM_EUNSTABLE = 5, /* a node is non-finite, has rho <= 0 or |u_a| >= 1 */
+  ELBM_ENOMEM = 6     /* host allocation failed */
+} elbm_status;
+
+typedef enum {
+  ELBM_STORE_F64 = 0,  /* FP64 populations, FP64 arithmetic */
+  ELBM_STORE_F32 = 1,  /* FP32 populations, FP32 arithmetic */
+  ELBM_STORE_F16S = 2, /* FP16 of f_i - W_i (round to nearest even), FP32 arithmetic */
+  ELBM_STORE_BF16S = 3 /* BF16 of f_i - W_i (round to nearest even), FP32 arithmetic */
+} elbm_storage;
+
+typedef enum { ELBM_FACE_WALL = 1, ELBM_FACE_INLET = 2, ELBM_FACE_OUTFLOW = 3 } elbm_face_kind;
+
+typedef struct elbm_ctx elbm_ctx;
+
+typedef struct {
+  int32_t dim;         /* 2 or 3 */
+  int32_t storage;     /* elbm_storage */
+  int64_t extent[3];   /* coarse nodes per axis (unused axes: 1) */
+  int32_t periodic[3]; /* nonzero: periodic axis */
+  double nu0;          /* kinematic viscosity of level 0, lattice units (Eq. visc) */
+  int32_t n_levels;    /* 1 .. 8; refinement ratio 2 between consecutive levels */
+} elbm_desc;
+
+/* Create a lattice (Sec. II.A, Sec. III.A for the level parameters). */
+elbm_status elbm_create(const elbm_desc *desc, elbm_ctx **out);
+/* Release host state and graphs; the caller's workspace is not freed. */
+elbm_status elbm_destroy(elbm_ctx *ctx);
+const char *elbm_status_string(elbm_status s);
+const char *elbm_last_error(const elbm_ctx *ctx);
+
+/* Boundary kind of a non-periodic face (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z).  u: inlet
+ * velocity (level-invariant); incoming populations at inlet nodes are set to the
+ * equilibrium at (rho=1, u); an outflow copies incoming populations from one node
+ * upstream.  Before elbm_finalize. */
+elbm_status elbm_set_face(elbm_ctx *ctx, int face, int kind, const double u[3]);
+
+/* Add a refinement block to level 1..L-1: the closed node box [lo, hi] in level
+ * coordinates.  The level's region is the union of its blocks (Sec. III: the
+ * overlapping region where both grids are present).  Faces that are not on a wall
+ * or spanning a periodic axis are interfaces and must lie on parent nodes (even
+ * coordinates).  A block spanning a periodic axis uses lo = 0, hi = period-1.
+ * Before elbm_finalize. */
+elbm_status elbm_add_block(elbm_ctx *ctx, int level, const int64_t lo[3], const int64_t hi[3]);
+
+/* Mark solid nodes of a level from a host uint8 mask over the box [lo, lo+n).
+ * Solid nodes reflect populations (halfway bounce-back); momentum exchanged with
+ * them is accumulated as drag.  Before elbm_finalize. */
+elbm_status elbm_set_solid(elbm_ctx *ctx, int level, const int64_t lo[3], const int64_t n[3],
+                           const uint8_t *mask_host);
+
+/* Uniform body-force density F (level-0 units), applied by the exact-difference
+ * method of Sec. III.A with du = F_l / rho and F_l = F / 2^l. */
+elbm_status elbm_set_force_uniform(elbm_ctx *ctx, const double F[3]);
+
+/* Validate the geometry (nesting, alignment, margins, boundary combinations) and
+ * build the node classes, interface lists and tick schedule on the host.  Returns
+ * the device workspace size the caller must provide to elbm_bind. */
+elbm_status elbm_finalize(elbm_ctx *ctx, size_t *workspace_bytes);
+
+elbm_status elbm_level_box(const elbm_ctx *ctx, int level, int64_t lo[3], int64_t n[3]);
+/* Node counts: n_nodes (stored nodes incl. solid), n_fluid, n_update (fluid nodes
+ * updated per level step), relaxation parameter beta_l (Eq. visc), bricks. */
+elbm_status elbm_level_info(const elbm_ctx *ctx, int level, int64_t *n_nodes, int64_t *n_fluid, double *beta,
+                            int64_t *n_bricks);
+/* Node classes over the level index box (int32): -1 absent, else bit0 solid, bit1
+ * parent ring (coalesced from the child), bits 2-3 distance to the own parent
+ * interface (0 outer layer, 1 inner layer, 3 bulk or level 0). */
+elbm_status elbm_node_class(const elbm_ctx *ctx, int level, int32_t *out_host);
+/* Owned-volume weights (level-0 volume units) over the level index box. */
+elbm_status elbm_weights(const elbm_ctx *ctx, int level, double *out_host);
+
+/* Bind the caller-owned device workspace (>= elbm_finalize bytes, 256-byte aligned)
+ * and HIP stream (hipStream_t; NULL = default stream).  Uploads tables. */
+elbm_status elbm_bind(elbm_ctx *ctx, void *workspace_dev, size_t bytes, void *hip_stream);
+
+/* Initial state of a level: f_i = f_i^eq(rho, u) (1 + noise_i) at every fluid node
+ * (Eq. feq_iso), from host arrays over the level index box (rho, u [D][box],
+ * noise [Q][box] or NULL).  Synchronous. */
+elbm_status elbm_init_fields(elbm_ctx *ctx, int level, const double *rho_host, const double *u_host,
+                             const double *noise_host);
+
+/* Per-node body-force density field of a level (device, [D][box], level-0 units),
+ * added to the uniform force; NULL removes it.  Asynchronous on the bound stream. */
+elbm_status elbm_set_force_field(elbm_ctx *ctx, int level, const double *F_dev);
+
+/* Advance n coarse steps (Sec. III.C): each is 2^(L-1) finest ticks, captured as one
+ * HIP graph unless graphs are disabled.  Asynchronous on the bound stream. */
+elbm_status elbm_advance(elbm_ctx *ctx, int n_coarse_steps);
+
+/* Macroscopic fields from the stored post-collision state: rho = sum f,
+ * u = sum c f / rho - du/2 (the mid-step velocity of the forcing scheme), gamma of the
+ * last collision (needs elbm_set_gamma_output).  Device arrays over the level box;
+ * absent and solid nodes are NaN.  Any pointer may be NULL.  Asynchronous. */
+elbm_status elbm_read_moments(elbm_ctx *ctx, int level, double *rho_dev, double *u_dev, double *gamma_dev);
+/* Post-collision populations f_i, device [Q][box], NaN at absent/solid nodes. */
+elbm_status elbm_read_populations(elbm_ctx *ctx, int level, double *f_dev);
+/* Populations at n level coordinates (host int64 [n][3]) into host double [n][Q];
+ * NaN where no fluid node exists.  Synchronous. */
+elbm_status elbm_sample_populations(elbm_ctx *ctx, int level, int64_t n, const int64_t *coords_host,
+                                    double *out_host);
+
+/* Mass and momentum over owned volumes (FP64 deterministic reduction) and the count
+ * of unstable nodes.  Synchronous. */
+elbm_status elbm_reduce(elbm_ctx *ctx, double *mass, double mom[3], int64_t *n_unstable);
+/* ELBM_EUNSTABLE if any node is non-finite, has rho <= 0 or |u_a| >= 1.  Synchronous. */
+elbm_status elbm_check(elbm_ctx *ctx);
+/* Momentum exchanged with solid nodes of a level (sum over its steps since the last
+ * reset of sum over links 2 c_i f'_i, level-l units) and the number of level steps.
+ * Synchronous. */
+elbm_status elbm_drag(elbm_ctx *ctx, int level, double F[3], int64_t *steps, int reset);
+
+/* Write gamma (Eq. gamma_min_approx) of every collision to a per-node buffer. */
+elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
+
+/* Launch configuration: use_graph (1: one graph per coarse step), workgroups per CU
+ * for the persistent stream-collide grid (0: one workgroup per brick), XCD-aware
+ * brick-to-workgroup mapping, threads per workgroup (64, 128 or 256; each thread
+ * covers 256/threads nodes of its brick), register-budget variant of the
+ * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD). */
+elbm_status elbm_set_launch(elbm_ctx *ctx, int use_graph, int wg_per_cu, int xcd_remap, int threads,
+                            int occupancy);
+/* Autotune the launch configuration by timing `steps` coarse steps per candidate;
+ * results cached in cache_path (one "key": [graph, wg_per_cu, xcd, threads, occupancy]
+ * line per workload shape; may be NULL).  The state is restored; drag accumulators
+ * are reset. */
+elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
+/* Time `steps` coarse steps with HIP events around every stream-collide launch;
+ * returns the total and summed stream-collide milliseconds and launch count.
+ * Synchronous. */
+elbm_status elbm_profile(elbm_ctx *ctx, int steps, double *ms_total, double *ms_stream_collide,
+                         int64_t *n_launches);
+/* Wait for the bound stream. */
+elbm_status elbm_synchronize(elbm_ctx *ctx);
+
+/* Checkpoint: state bytes, copy state to/from caller device memory (async). */
+elbm_status elbm_state_bytes(const elbm_ctx *ctx, size_t *bytes);
+elbm_status elbm_save_state(elbm_ctx *ctx, void *dev_dst);
+elbm_status elbm_load_state(elbm_ctx *ctx, const void *dev_src);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1694 @@
+// elbm.cpp -- host runtime and C ABI of the refined KBC lattice Boltzmann library.
+//
+// Geometry (Sec. III): a level's region is the union of its blocks; child nodes at
+// fine Chebyshev distance 0 / 1 from the region boundary (ignoring positions outside
+// the domain) form the outer / inner interface layers; the parent keeps its nodes
+// up to fine distance 2 inside the child region, those at distance 2 being the ring
+// rebuilt from co-located child nodes (twin nodes x_t,cf); outer-layer child nodes
+// on parent positions are the twins x_t,fc; the other interface nodes are the
+// reconstruction nodes x_r.  Distances are computed per brick from windowed
+// membership bitmaps and 3-D prefix sums.
+//
+// Schedule (Sec. III.C, recursive over levels): one coarse step is 2^(L-1) ticks of
+// the finest level; level l arrives every 2^(L-1-l) ticks.  At a tick, every arriving
+// level stream-collides its bulk nodes (pull from its previous post-collision
+// buffer); a level whose parent does not arrive is at its first substep and also
+// collides its inner interface layer (the outer layer is skipped, step 1).  For each
+// arriving parent/child pair the post-stream states of coarse-aligned points are
+// gathered, then the child interface layers are reconstructed (steps 3-4) and the
+// parent ring coalesced, and those nodes collide (step 5).  Everything reads the
+// previous buffers and writes the next ones, so the bulk and coupling launches of a
+// tick are independent and run as parallel graph branches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/elbm.h"
+#include "elbm_dev.hpp"
+
+using namespace elbm;
+
+namespace {
+
+struct Box {
+  int64_t lo[3], hi[3];
+};
+struct SolidSpec {
+  int64_t lo[3], n[3];
+  std::vector<uint8_t> mask;
+};
+
+struct Level {
+  std::vector<Box> boxes;
+  std::vector<SolidSpec> solids;
+  int64_t blo[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+  int full[3] = {0, 0, 0};
+  int64_t gdim[3] = {1, 1, 1};
+  std::vector<int32_t> bgrid;  // brick grid -> brick id
+  std::vector<int32_t> borg;   // [nb*3] brick origin relative to blo
+  int32_t nb = 0;
+  std::vector<uint8_t> cls;
+  std::vector<uint32_t> mask;
+  std::vector<float> weight;
+  std::vector<int32_t> nbr;
+  std::vector<uint8_t> exists, pd, ring, solid;
+  double beta = 1.0;
+  int64_t n_nodes = 0, n_fluid = 0, n_update = 0;
+  std::vector<WorkItem> items1, items2;
+  bool any_drag = false;
+  size_t o_pop[2] = {0, 0}, o_cls = 0, o_mask = 0, o_w = 0, o_nbr = 0, o_force = 0, o_gamma = 0, o_drag = 0,
+         o_borg = 0;
+  bool force_on = false;
+};
+
+struct Pair {
+  std::vector<GPoint> pts;
+  std::vector<CItem> items;
+  double fac_pc = 1, fac_cp = 1;
+};
+
+struct Tick {
+  int lmin;
+  size_t sc_off, sc_n, gp_off, gp_n, ci_off, ci_n;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct elbm_ctx {
+  int D = 3, Q = 27, L = 1, storage = ST_F32;
+  int64_t N[3] = {1, 1, 1};
+  int periodic[3] = {0, 0, 0};
+  double nu0 = 0;
+  int face_kind[6] = {0, 0, 0, 0, 0, 0};
+  double face_u[6][3] = {};
+  double Fu[3] = {0, 0, 0};
+  Level lev[MAXL];
+  std::vector<Pair> pairs;
+  std::vector<Tick> ticks;
+  std::vector<WorkItem> sc_all, red_items;
+  std::vector<GPoint> gp_all;
+  std::vector<CItem> ci_all;
+  std::vector<StencilEntry> sten;
+  int stage_cols = 0;
+  bool finalized = false, bound = false;
+  std::string err;
+  // workspace layout
+  size_t ws_need = 0, o_levstatic = 0, o_pairstatic = 0, o_sc = 0, o_gp = 0, o_ci = 0, o_sten = 0, o_stage = 0,
+         o_redit = 0, o_part = 0, o_res = 0, o_tmp = 0;
+  size_t tmp_bytes = 0;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr, side = nullptr, cap = nullptr;
+  hipEvent_t ev_fork[64], ev_join[64];
+  int n_events = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_valid = false;
+  int parity = 0;  // buffer index of level 0
+  int64_t drag_steps[MAXL] = {};
+  // launch config
+  int use_graph = 1, wg_per_cu = 0, xcd_remap = 1, threads = 256, occ = 1;
+  bool gamma_on = false;
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  int cu_count = 256;
+};
+
+#define FAIL(ctx, code, ...)                                          \
+  do {                                                                \
+    char _b[512];                                                     \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                            \
+    (ctx)->err = _b;                                                  \
+    return code;                                                      \
+  } while (0)
+
+#define HIPCK(ctx, call)                                                          \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess) FAIL(ctx, ELBM_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+#define LCK(ctx, call)                                                                          \
+  do {                                                                                          \
+    int _e = (call);                                                                            \
+    if (_e) FAIL(ctx, ELBM_EDEVICE, "%s: %s", #call, hipGetErrorString((hipError_t)_e));       \
+  } while (0)
+
+namespace {
+
+// ------------------------------------------------------------------ geometry helpers
+int64_t period(const elbm_ctx *c, int l, int a) { return c->N[a] << l; }
+int64_t extent(const elbm_ctx *c, int l, int a) {
+  if (a >= c->D) return 1;
+  return c->periodic[a] ? (c->N[a] << l) : ((c->N[a] - 1) << l) + 1;
+}
+int64_t pmod(int64_t x, int64_t p) {
+  int64_t r = x % p;
+  return r < 0 ? r + p : r;
+}
+// canonical position (periodic wrap); false if outside a non-periodic axis
+bool to_domain(const elbm_ctx *c, int l, int64_t x[3]) {
+  for (int a = 0; a < 3; ++a) {
+    if (a >= c->D) {
+      if (x[a] != 0) return false;
+      continue;
+    }
+    if (c->periodic[a]) x[a] = pmod(x[a], period(c, l, a));
+    else if (x[a] < 0 || x[a] >= extent(c, l, a)) return false;
+  }
+  return true;
+}
+bool box_spans(const elbm_ctx *c, int l, const Box &b, int a) {
+  return c->periodic[a] && b.hi[a] - b.lo[a] >= period(c, l, a) - 1;
+}
+// canonical in-domain x inside the union of level-l blocks (level 0: everywhere)
+bool in_blocks(const elbm_ctx *c, int l, const int64_t x[3]) {
+  if (l == 0) return true;
+  for (const Box &b : c->lev[l].boxes) {
+    bool in = true;
+    for (int a = 0; a < c->D && in; ++a) {
+      if (c->periodic[a]) {
+        if (box_spans(c, l, b, a)) continue;
+        in = pmod(x[a] - b.lo[a], period(c, l, a)) <= b.hi[a] - b.lo[a];
+      } else {
+        in = x[a] >= b.lo[a] && x[a] <= b.hi[a];
+      }
+    }
+    if (in) return true;
+  }
+  return false;
+}
+// member: in the domain and in the level region
+bool member(const elbm_ctx *c, int l, const int64_t xin[3]) {
+  int64_t x[3] = {xin[0], xin[1], xin[2]};
+  return to_domain(c, l, x) && in_blocks(c, l, x);
+}
+// "bad" position for distance purposes: in the domain but outside the region
+bool bad_pos(const elbm_ctx *c, int l, const int64_t xin[3]) {
+  int64_t x[3] = {xin[0], xin[1], xin[2]};
+  if (!to_domain(c, l, x)) return false;
+  return !in_blocks(c, l, x);
+}
+// direct distance (capped at 3) of a member position; -1 if not a member
+int dist_direct(const elbm_ctx *c, int l, const int64_t x[3]) {
+  if (!member(c, l, x)) return -1;
+  if (l == 0) return 3;
+  int k;
+  for (k = 1; k <= 3; ++k) {
+    const int kz = c->D == 3 ? k : 0;
+    for (int64_t dz = -kz; dz <= kz; ++dz)
+      for (int64_t dy = -k; dy <= k; ++dy)
+        for (int64_t dx = -k; dx <= k; ++dx) {
+          if (std::max(std::max(std::llabs(dx), std::llabs(dy)), std::llabs(dz)) != k) continue;
+          int64_t y[3] = {x[0] + dx, x[1] + dy, x[2] + dz};
+          if (bad_pos(c, l, y)) return k - 1;
+        }
+  }
+  return 3;
+}
+
+// Windowed prefix sums of "bad" positions: counts over boxes in O(1).
+struct Window {
+  int64_t lo[3], n[3];
+  std::vector<int32_t> S;  // (n+1)^3 inclusive prefix
+  void build(const elbm_ctx *c, int l, const int64_t wlo[3], const int64_t whi[3]) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = wlo[a];
+      n[a] = whi[a] - wlo[a] + 1;
+    }
+    S.assign((size_t)(n[0] + 1) * (n[1] + 1) * (n[2] + 1), 0);
+    auto at = [&](int64_t i, int64_t j, int64_t k) -> int32_t & {
+      return S[(size_t)i + (size_t)(n[0] + 1) * ((size_t)j + (size_t)(n[1] + 1) * (size_t)k)];
+    };
+    for (int64_t k = 1; k <= n[2]; ++k)
+      for (int64_t j = 1; j <= n[1]; ++j)
+        for (int64_t i = 1; i <= n[0]; ++i) {
+          int64_t p[3] = {lo[0] + i - 1, lo[1] + j - 1, lo[2] + k - 1};
+          int32_t v = l == 0 ? 0 : (int32_t)bad_pos(c, l, p);
+          at(i, j, k) = v + at(i - 1, j, k) + at(i, j - 1, k) + at(i, j, k - 1) - at(i - 1, j - 1, k) -
+                        at(i - 1, j, k - 1) - at(i, j - 1, k - 1) + at(i - 1, j - 1, k - 1);
+        }
+  }
+  int32_t count(const int64_t a[3], const int64_t b[3]) const {  // inclusive, must lie in the window
+    int64_t i0 = a[0] - lo[0], j0 = a[1] - lo[1], k0 = a[2] - lo[2];
+    int64_t i1 = b[0] - lo[0] + 1, j1 = b[1] - lo[1] + 1, k1 = b[2] - lo[2] + 1;
+    auto at = [&](int64_t i, int64_t j, int64_t k) -> int32_t {
+      return S[(size_t)i + (size_t)(n[0] + 1) * ((size_t)j + (size_t)(n[1] + 1) * (size_t)k)];
+    };
+    return at(i1, j1, k1) - at(i0, j1, k1) - at(i1, j0, k1) - at(i1, j1, k0) + at(i0, j0, k1) + at(i0, j1, k0) +
+           at(i1, j0, k0) - at(i0, j0, k0);
+  }
+  // distance capped at 3 for a member position (caller checks membership)
+  int dist(int D, const int64_t x[3]) const {
+    for (int k = 1; k <= 3; ++k) {
+      int64_t a[3] = {x[0] - k, x[1] - k, D == 3 ? x[2] - k : x[2]};
+      int64_t b[3] = {x[0] + k, x[1] + k, D == 3 ? x[2] + k : x[2]};
+      if (count(a, b)) return k - 1;
+    }
+    return 3;
+  }
+};
+
+template <int D> struct BK {
+  static constexpr int X = Brick<D>::BX, Y = Brick<D>::BY, Z = Brick<D>::BZ;
+};
+int bdim(int D, int a) {
+  if (D == 2) return a == 0 ? Brick<2>::BX : (a == 1 ? Brick<2>::BY : 1);
+  return a == 0 ? Brick<3>::BX : (a == 1 ? Brick<3>::BY : Brick<3>::BZ);
+}
+
+int vel(int D, int i, int a) {
+  if (a == 0) return i % 3 - 1;
+  if (a == 1) return (i / 3) % 3 - 1;
+  return D == 3 ? i / 9 - 1 : 0;
+}
+double wgt(int D, int i) {
+  double w = 1;
+  for (int a = 0; a < D; ++a) w *= vel(D, i, a) == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+  return w;
+}
+
+// equilibrium minus weights at (rho=1, u), host double (inlet populations)
+void heq_host(int D, const double u[3], double *h) {
+  const int Q = D == 2 ? 9 : 27;
+  double a[3][3];
+  for (int ax = 0; ax < 3; ++ax) {
+    double t = 3 * u[ax] * u[ax], sig = t / (1 + std::sqrt(1 + t));
+    a[ax][0] = 2 * sig - 3 * u[ax];
+    a[ax][1] = -sig;
+    a[ax][2] = 2 * sig + 3 * u[ax];
+  }
+  for (int i = 0; i < Q; ++i) {
+    double p = 1;
+    for (int ax = 0; ax < D; ++ax) p *= 1 + a[ax][vel(D, i, ax) + 1];
+    h[i] = wgt(D, i) * (p - 1);
+  }
+}
+
+struct NodeRef {
+  int32_t brick = -1;
+  int32_t node = 0;
+};
+
+NodeRef locate(const elbm_ctx *c, int l, const int64_t xin[3]) {
+  NodeRef r;
+  int64_t x[3] = {xin[0], xin[1], xin[2]};
+  if (!to_domain(c, l, x)) return r;
+  const Level &L = c->lev[l];
+  int64_t g[3], loc[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t p = x[a] - L.blo[a];
+    if (p < 0 || p >= L.bn[a]) return r;
+    g[a] = p / bdim(c->D, a);
+    loc[a] = p % bdim(c->D, a);
+  }
+  int32_t b = L.bgrid[(size_t)g[0] + (size_t)L.gdim[0] * ((size_t)g[1] + (size_t)L.gdim[1] * (size_t)g[2])];
+  if (b < 0) return r;
+  int32_t n = (int32_t)(loc[0] + bdim(c->D, 0) * (loc[1] + bdim(c->D, 1) * loc[2]));
+  if (!L.exists[(size_t)b * BN + n]) return r;
+  r.brick = b;
+  r.node = n;
+  return r;
+}
+
+elbm_status build_level_geometry(elbm_ctx *c, int l);
+elbm_status build_level_links(elbm_ctx *c, int l);
+elbm_status build_pairs(elbm_ctx *c);
+void build_schedule(elbm_ctx *c);
+void build_layout(elbm_ctx *c);
+
+elbm_status build_level_geometry(elbm_ctx *c, int l) {
+  Level &L = c->lev[l];
+  const int D = c->D;
+  // index box
+  for (int a = 0; a < 3; ++a) {
+    L.full[a] = 0;
+    if (a >= D) {
+      L.blo[a] = 0;
+      L.bn[a] = 1;
+      continue;
+    }
+    if (l == 0) {
+      L.blo[a] = 0;
+      L.bn[a] = extent(c, 0, a);
+      L.full[a] = c->periodic[a];
+      continue;
+    }
+    bool whole = false;
+    int64_t mn = INT64_MAX, mx = INT64_MIN;
+    for (const Box &b : L.boxes) {
+      if (c->periodic[a] && (box_spans(c, l, b, a) || b.hi[a] >= period(c, l, a))) whole = true;
+      mn = std::min(mn, b.lo[a]);
+      mx = std::max(mx, b.hi[a]);
+    }
+    if (whole) {
+      L.blo[a] = 0;
+      L.bn[a] = period(c, l, a);
+      L.full[a] = 1;
+    } else {
+      L.blo[a] = mn;
+      L.bn[a] = mx - mn + 1;
+    }
+  }
+  for (int a = 0; a < D; ++a) {
+    if (L.full[a] && L.bn[a] % bdim(D, a))
+      FAIL(c, ELBM_EINVAL, "level %d: periodic axis %d has %lld nodes, not a multiple of the brick size %d", l, a,
+           (long long)L.bn[a], bdim(D, a));
+  }
+  for (int a = 0; a < 3; ++a) L.gdim[a] = (L.bn[a] + bdim(D, a) - 1) / bdim(D, a);
+  const size_t ng = (size_t)L.gdim[0] * L.gdim[1] * L.gdim[2];
+  // candidate bricks
+  std::vector<uint8_t> cand(ng, l == 0 ? 1 : 0);
+  if (l > 0) {
+    for (const Box &b : L.boxes) {
+      // per axis, list of index-box coordinate ranges covered by the box
+      std::vector<std::pair<int64_t, int64_t>> rng[3];
+      for (int a = 0; a < 3; ++a) {
+        if (a >= D) {
+          rng[a].push_back({0, 0});
+          continue;
+        }
+        if (c->periodic[a] && box_spans(c, l, b, a)) {
+          rng[a].push_back({0, L.bn[a] - 1});
+        } else if (c->periodic[a] && L.full[a]) {
+          int64_t P = period(c, l, a);
+          int64_t lo = b.lo[a], hi = b.hi[a];
+          if (hi < P) rng[a].push_back({lo, hi});
+          else {
+            rng[a].push_back({lo, P - 1});
+            rng[a].push_back({0, hi - P});
+          }
+        } else {
+          rng[a].push_back({b.lo[a] - L.blo[a], b.hi[a] - L.blo[a]});
+        }
+      }
+      for (auto rx : rng[0])
+        for (auto ry : rng[1])
+          for (auto rz : rng[2])
+            for (int64_t gz = rz.first / bdim(D, 2); gz <= rz.second / bdim(D, 2); ++gz)
+              for (int64_t gy = ry.first / bdim(D, 1); gy <= ry.second / bdim(D, 1); ++gy)
+                for (int64_t gx = rx.first / bdim(D, 0); gx <= rx.second / bdim(D, 0); ++gx)
+                  cand[(size_t)gx + L.gdim[0] * ((size_t)gy + L.gdim[1] * (size_t)gz)] = 1;
+    }
+  }
+  // bounding box of the child level's blocks (level l+1 coordinates) to skip work
+  const bool has_child = l + 1 < c->L;
+  L.bgrid.assign(ng, -1);
+  L.borg.clear();
+  L.exists.clear();
+  L.pd.clear();
+  L.ring.clear();
+  L.weight.clear();
+  L.nb = 0;
+  std::vector<uint8_t> ex(BN), pdv(BN), rg(BN);
+  std::vector<float> wv(BN);
+  const double base = std::ldexp(1.0, -l * D);
+  for (int64_t gz = 0; gz < L.gdim[2]; ++gz)
+    for (int64_t gy = 0; gy < L.gdim[1]; ++gy)
+      for (int64_t gx = 0; gx < L.gdim[0]; ++gx) {
+        const size_t gi = (size_t)gx + L.gdim[0] * ((size_t)gy + L.gdim[1] * (size_t)gz);
+        if (!cand[gi]) continue;
+        int64_t o[3] = {gx * bdim(D, 0), gy * bdim(D, 1), gz * bdim(D, 2)};
+        int64_t x0[3], x1[3];  // level coordinates of the brick
+        for (int a = 0; a < 3; ++a) {
+          x0[a] = L.blo[a] + o[a];
+          x1[a] = x0[a] + bdim(D, a) - 1;
+        }
+        Window wa, wb;
+        int64_t m = 3;
+        int64_t alo[3] = {x0[0] - m, x0[1] - m, D == 3 ? x0[2] - m : 0};
+        int64_t ahi[3] = {x1[0] + m, x1[1] + m, D == 3 ? x1[2] + m : 0};
+        if (l > 0) wa.build(c, l, alo, ahi);
+        if (has_child) {
+          int64_t blo2[3] = {2 * x0[0] - m, 2 * x0[1] - m, D == 3 ? 2 * x0[2] - m : 0};
+          int64_t bhi2[3] = {2 * x1[0] + m, 2 * x1[1] + m, D == 3 ? 2 * x1[2] + m : 0};
+          wb.build(c, l + 1, blo2, bhi2);
+        }
+        bool any = false;
+        for (int n = 0; n < BN; ++n) {
+          int64_t loc[3] = {n % bdim(D, 0), (n / bdim(D, 0)) % bdim(D, 1), n / (bdim(D, 0) * bdim(D, 1))};
+          int64_t x[3] = {x0[0] + loc[0], x0[1] + loc[1], x0[2] + loc[2]};
+          ex[n] = 0;
+          pdv[n] = 0;
+          rg[n] = 0;
+          wv[n] = 0;
+          if (loc[2] >= bdim(D, 2)) continue;
+          bool inside = true;
+          for (int a = 0; a < 3; ++a) inside = inside && (x[a] - L.blo[a] < L.bn[a]);
+          if (!inside || !member(c, l, x)) continue;
+          int dch = -1;
+          if (has_child) {
+            int64_t y[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
+            if (member(c, l + 1, y)) dch = wb.dist(D, y);
+          }
+          if (dch >= 3) continue;  // deep inside the child: no parent node (Sec. III)
+          ex[n] = 1;
+          any = true;
+          rg[n] = dch == 2;
+          int d = l > 0 ? wa.dist(D, x) : 3;
+          pdv[n] = (uint8_t)d;
+          // owned-volume weight: the child owns its region eroded by one fine spacing;
+          // sub-cell sigma of x is owned iff the 4^D node block [x-1,x+2] / [x-2,x+1]
+          // (per axis, by sign) contains no in-domain position outside the region
+          double wt = base;
+          if (rg[n]) wt = 0;
+          else if (l > 0 && d < 2) {
+            int cnt = 0, tot = 1 << D;
+            for (int s = 0; s < tot; ++s) {
+              int64_t a0[3] = {x[0], x[1], x[2]}, a1[3] = {x[0], x[1], x[2]};
+              for (int a = 0; a < D; ++a) {
+                bool plus = (s >> a) & 1;
+                a0[a] = x[a] + (plus ? -1 : -2);
+                a1[a] = x[a] + (plus ? 2 : 1);
+              }
+              cnt += wa.count(a0, a1) == 0;
+            }
+            wt = base * cnt / tot;
+          }
+          wv[n] = (float)wt;
+        }
+        if (!any) continue;
+        const int32_t b = L.nb++;
+        L.bgrid[gi] = b;
+        L.borg.push_back((int32_t)o[0]);
+        L.borg.push_back((int32_t)o[1]);
+        L.borg.push_back((int32_t)o[2]);
+        L.exists.insert(L.exists.end(), ex.begin(), ex.end());
+        L.pd.insert(L.pd.end(), pdv.begin(), pdv.end());
+        L.ring.insert(L.ring.end(), rg.begin(), rg.end());
+        L.weight.insert(L.weight.end(), wv.begin(), wv.end());
+      }
+  L.solid.assign((size_t)L.nb * BN, 0);
+  for (const SolidSpec &s : L.solids) {
+    for (int64_t z = 0; z < s.n[2]; ++z)
+      for (int64_t y = 0; y < s.n[1]; ++y)
+        for (int64_t x = 0; x < s.n[0]; ++x) {
+          if (!s.mask[(size_t)x + s.n[0] * ((size_t)y + s.n[1] * (size_t)z)]) continue;
+          int64_t p[3] = {s.lo[0] + x, s.lo[1] + y, s.lo[2] + z};
+          NodeRef r = locate(c, l, p);
+          if (r.brick < 0)
+            FAIL(c, ELBM_EINVAL, "level %d: solid node (%lld,%lld,%lld) is not a node of this level", l,
+                 (long long)p[0], (long long)p[1], (long long)p[2]);
+          size_t k = (size_t)r.brick * BN + r.node;
+          if (L.pd[k] < 2 || L.ring[k])
+            FAIL(c, ELBM_EINVAL, "level %d: solid node (%lld,%lld,%lld) lies on an interface layer", l,
+                 (long long)p[0], (long long)p[1], (long long)p[2]);
+          L.solid[k] = 1;
+          L.weight[k] = 0;
+        }
+  }
+  L.beta = 1.0 / (6.0 * c->nu0 * std::ldexp(1.0, l) + 1.0);  // Eq. visc with nu_l = 2^l nu0
+  return ELBM_OK;
+}
+
+elbm_status build_level_links(elbm_ctx *c, int l) {
+  Level &L = c->lev[l];
+  const int D = c->D, Q = c->Q;
+  L.cls.assign((size_t)L.nb * BN, 0);
+  L.mask.assign((size_t)L.nb * BN, 0);
+  L.n_nodes = L.n_fluid = L.n_update = 0;
+  L.any_drag = false;
+  L.items1.clear();
+  L.items2.clear();
+  for (int32_t b = 0; b < L.nb; ++b) {
+    bool m1 = false, m2 = false, dr = false;
+    for (int n = 0; n < BN; ++n) {
+      const size_t k = (size_t)b * BN + n;
+      if (!L.exists[k]) continue;
+      L.n_nodes++;
+      if (L.solid[k]) continue;
+      L.n_fluid++;
+      int64_t x[3];
+      int64_t loc[3] = {n % bdim(D, 0), (n / bdim(D, 0)) % bdim(D, 1), n / (bdim(D, 0) * bdim(D, 1))};
+      for (int a = 0; a < 3; ++a) x[a] = L.blo[a] + L.borg[3 * b + a] + loc[a];
+      int mode = 2;
+      if (L.ring[k] || L.pd[k] == 0) mode = 0;
+      else if (L.pd[k] == 1) mode = 1;
+      uint32_t bb = 0, inl = 0, outm = 0, solidlinks = 0, walllinks = 0;
+      for (int i = 0; i < Q; ++i) {
+        int64_t y[3];
+        for (int a = 0; a < 3; ++a) y[a] = x[a] - vel(D, i, a);
+        int kind = 0;  // 0 node, 1 wall, 2 inlet, 3 outflow
+        for (int a = 0; a < D; ++a) {
+          if (c->periodic[a]) continue;
+          int face = -1;
+          if (y[a] < 0) face = 2 * a;
+          else if (y[a] > extent(c, l, a) - 1) face = 2 * a + 1;
+          if (face < 0) continue;
+          int fk = c->face_kind[face];
+          if (fk == ELBM_FACE_WALL) kind = 1;
+          else if (fk == ELBM_FACE_INLET && kind != 1) kind = 2;
+          else if (fk == ELBM_FACE_OUTFLOW) {
+            if (kind == 0) kind = 3;
+            y[a] += (face & 1) ? -1 : 1;
+          }
+        }
+        if (kind == 1) {
+          bb |= 1u << i;
+          walllinks |= 1u << i;
+          continue;
+        }
+        if (kind == 2) {
+          inl |= 1u << i;
+          continue;
+        }
+        if (kind == 3) outm |= 1u << i;
+        NodeRef r = locate(c, l, y);
+        if (r.brick >= 0 && L.solid[(size_t)r.brick * BN + r.node]) {
+          if (kind == 3)
+            FAIL(c, ELBM_EINVAL, "level %d: outflow source is solid at (%lld,%lld,%lld)", l, (long long)x[0],
+                 (long long)x[1], (long long)x[2]);
+          bb |= 1u << i;
+          solidlinks |= 1u << i;
+          continue;
+        }
+        if (mode > 0 && r.brick < 0)
+          FAIL(c, ELBM_EINVAL,
+               "level %d: node (%lld,%lld,%lld) pulls population %d from a position with no node (nesting margin "
+               "or interface alignment violated)",
+               l, (long long)x[0], (long long)x[1], (long long)x[2], i);
+      }
+      const int kinds = (bb != 0) + (inl != 0) + (outm != 0);
+      if (kinds > 1)
+        FAIL(c, ELBM_EINVAL, "level %d: node (%lld,%lld,%lld) mixes wall/solid, inlet and outflow links", l,
+             (long long)x[0], (long long)x[1], (long long)x[2]);
+      if (solidlinks && walllinks)
+        FAIL(c, ELBM_EINVAL, "level %d: node (%lld,%lld,%lld) touches both a wall and a solid", l,
+             (long long)x[0], (long long)x[1], (long long)x[2]);
+      if (mode == 0 && kinds)
+        FAIL(c, ELBM_EINVAL, "level %d: interface node (%lld,%lld,%lld) touches a boundary", l, (long long)x[0],
+             (long long)x[1], (long long)x[2]);
+      uint8_t cl = (uint8_t)mode | CLS_FLUID;
+      if (bb) cl |= CLS_LINKS;
+      if (inl) cl |= CLS_INLET;
+      if (outm) cl |= CLS_OUTFLOW;
+      if (solidlinks) {
+        cl |= CLS_DRAG;
+        dr = true;
+      }
+      L.cls[k] = cl;
+      L.mask[k] = bb | inl | outm;
+      if (mode >= 1) m1 = true;
+      if (mode == 2) m2 = true;
+      if (mode > 0 || L.ring[k] || L.pd[k] <= 1) L.n_update++;
+    }
+    WorkItem w;
+    w.brick = b;
+    w.level = (uint8_t)l;
+    w.drag = dr;
+    w.pad = 0;
+    if (m1) {
+      w.thr = 1;
+      L.items1.push_back(w);
+    }
+    if (m2) {
+      w.thr = 2;
+      L.items2.push_back(w);
+    }
+    L.any_drag = L.any_drag || dr;
+  }
+  // neighbour table (periodic wrap on whole-period axes)
+  L.nbr.assign((size_t)L.nb * 27, -1);
+  for (int32_t b = 0; b < L.nb; ++b) {
+    int64_t g[3] = {L.borg[3 * b] / bdim(D, 0), L.borg[3 * b + 1] / bdim(D, 1), L.borg[3 * b + 2] / bdim(D, 2)};
+    for (int k = 0; k < 27; ++k) {
+      int64_t q[3] = {g[0] + k % 3 - 1, g[1] + (k / 3) % 3 - 1, g[2] + k / 9 - 1};
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        if (q[a] < 0 || q[a] >= L.gdim[a]) {
+          if (L.full[a] && a < D) q[a] = pmod(q[a], L.gdim[a]);
+          else ok = false;
+        }
+      }
+      if (!ok) continue;
+      L.nbr[(size_t)b * 27 + k] = L.bgrid[(size_t)q[0] + L.gdim[0] * ((size_t)q[1] + L.gdim[1] * (size_t)q[2])];
+    }
+  }
+  return ELBM_OK;
+}
+
+bool plain_bulk(const elbm_ctx *c, int l, NodeRef r) {
+  if (r.brick < 0) return false;
+  const Level &L = c->lev[l];
+  const size_t k = (size_t)r.brick * BN + r.node;
+  const uint8_t cl = L.cls[k];
+  return (cl & CLS_FLUID) && (cl & CLS_MODE) == 2 && !(cl & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) && !L.ring[k];
+}
+
+elbm_status build_pairs(elbm_ctx *c) {
+  const int D = c->D;
+  c->pairs.assign(c->L > 1 ? c->L - 1 : 0, Pair());
+  c->sten.clear();
+  int slots = 0;
+  for (int p = 0; p + 1 < c->L; ++p) {
+    Pair &P = c->pairs[p];
+    const Level &Lp = c->lev[p], &Lc = c->lev[p + 1];
+    P.fac_pc = Lp.beta / (2.0 * Lc.beta);  // Eq. f_neq_rescaling_iso with r = 2
+    P.fac_cp = 2.0 * Lc.beta / Lp.beta;
+    std::unordered_map<uint64_t, int32_t> slot_of;
+    auto point = [&](const int64_t X[3], int32_t &slot) -> elbm_status {
+      int64_t xc[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+      int lvl;
+      NodeRef r;
+      int dch = member(c, p + 1, xc) ? dist_direct(c, p + 1, xc) : -1;
+      if (dch >= 2) {
+        lvl = p + 1;
+        r = locate(c, p + 1, xc);
+      } else {
+        lvl = p;
+        r = locate(c, p, X);
+      }
+      if (!plain_bulk(c, lvl, r))
+        FAIL(c, ELBM_EINVAL,
+             "interface %d/%d: interpolation point (%lld,%lld,%lld) has no plain bulk node on level %d (nesting "
+             "margin too small or boundary too close)",
+             p, p + 1, (long long)X[0], (long long)X[1], (long long)X[2], lvl);
+      uint64_t key = ((uint64_t)lvl << 56) ^ ((uint64_t)r.brick << 16) ^ (uint64_t)r.node;
+      auto it = slot_of.find(key);
+      if (it != slot_of.end()) {
+        slot = it->second;
+        return ELBM_OK;
+      }
+      GPoint g;
+      g.brick = r.brick;
+      g.node = (uint16_t)r.node;
+      g.level = (uint8_t)lvl;
+      g.pair = (uint8_t)p;
+      g.slot = slots++;
+      P.pts.push_back(g);
+      slot_of[key] = g.slot;
+      slot = g.slot;
+      return ELBM_OK;
+    };
+    static const float w4[4] = {-1.0f / 16, 9.0f / 16, 9.0f / 16, -1.0f / 16};
+    // fine interface layers
+    for (int32_t b = 0; b < Lc.nb; ++b)
+      for (int n = 0; n < BN; ++n) {
+        const size_t k = (size_t)b * BN + n;
+        if (!Lc.exists[k] || Lc.solid[k] || Lc.pd[k] > 1) continue;
+        int64_t loc[3] = {n % bdim(D, 0), (n / bdim(D, 0)) % bdim(D, 1), n / (bdim(D, 0) * bdim(D, 1))};
+        int64_t x[3];
+        for (int a = 0; a < 3; ++a) x[a] = Lc.blo[a] + Lc.borg[3 * b + a] + loc[a];
+        int64_t xw[3] = {x[0], x[1], x[2]};
+        to_domain(c, p + 1, xw);
+        int npt[3] = {1, 1, 1};
+        int64_t pts[3][4];
+        float wts[3][4];
+        for (int a = 0; a < 3; ++a) {
+          if (a < D && (xw[a] & 1)) {
+            npt[a] = 4;
+            for (int q = 0; q < 4; ++q) {
+              pts[a][q] = (xw[a] - 3 + 2 * q) / 2;
+              wts[a][q] = w4[q];
+            }
+          } else {
+            pts[a][0] = xw[a] / 2;
+            wts[a][0] = 1.0f;
+          }
+        }
+        CItem it;
+        it.brick = b;
+        it.node = (uint16_t)n;
+        it.level = (uint8_t)(p + 1);
+        it.kind = 0;
+        it.a = (int32_t)c->sten.size();
+        it.b = npt[0] * npt[1] * npt[2];
+        for (int qz = 0; qz < npt[2]; ++qz)
+          for (int qy = 0; qy < npt[1]; ++qy)
+            for (int qx = 0; qx < npt[0]; ++qx) {
+              int64_t X[3] = {pts[0][qx], pts[1][qy], pts[2][qz]};
+              int32_t slot;
+              elbm_status s = point(X, slot);
+              if (s) return s;
+              StencilEntry e;
+              e.slot = slot;
+              e.w = wts[0][qx] * wts[1][qy] * wts[2][qz];
+              c->sten.push_back(e);
+            }
+        P.items.push_back(it);
+      }
+    // uniform stencil sizes within a wavefront: longest stencils first
+    std::stable_sort(P.items.begin(), P.items.end(), [](const CItem &x, const CItem &y) { return x.b > y.b; });
+    // parent ring
+    for (int32_t b = 0; b < Lp.nb; ++b)
+      for (int n = 0; n < BN; ++n) {
+        const size_t k = (size_t)b * BN + n;
+        if (!Lp.exists[k] || !Lp.ring[k]) continue;
+        int64_t loc[3] = {n % bdim(D, 0), (n / bdim(D, 0)) % bdim(D, 1), n / (bdim(D, 0) * bdim(D, 1))};
+        int64_t x[3];
+        for (int a = 0; a < 3; ++a) x[a] = Lp.blo[a] + Lp.borg[3 * b + a] + loc[a];
+        int64_t xc[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
+        NodeRef r = locate(c, p + 1, xc);
+        if (!plain_bulk(c, p + 1, r))
+          FAIL(c, ELBM_EINVAL, "interface %d/%d: ring node (%lld,%lld,%lld) has no plain fine twin", p, p + 1,
+               (long long)x[0], (long long)x[1], (long long)x[2]);
+        if (Lp.cls[k] & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW))
+          FAIL(c, ELBM_EINVAL, "interface %d/%d: ring node touches a boundary", p, p + 1);
+        CItem it;
+        it.brick = b;
+        it.node = (uint16_t)n;
+        it.level = (uint8_t)p;
+        it.kind = 1;
+        it.a = r.brick;
+        it.b = r.node;
+        P.items.push_back(it);
+      }
+  }
+  c->stage_cols = slots;
+  return ELBM_OK;
+}
+
+void build_schedule(elbm_ctx *c) {
+  c->ticks.clear();
+  c->sc_all.clear();
+  c->gp_all.clear();
+  c->ci_all.clear();
+  // pair lists laid out by parent level so that the pairs of a tick are contiguous
+  std::vector<size_t> gp_start(c->L + 1, 0), ci_start(c->L + 1, 0);
+  for (int p = 0; p + 1 < c->L; ++p) {
+    gp_start[p] = c->gp_all.size();
+    ci_start[p] = c->ci_all.size();
+    c->gp_all.insert(c->gp_all.end(), c->pairs[p].pts.begin(), c->pairs[p].pts.end());
+    c->ci_all.insert(c->ci_all.end(), c->pairs[p].items.begin(), c->pairs[p].items.end());
+  }
+  const int pL = c->L > 1 ? c->L - 1 : 0;
+  gp_start[pL] = c->gp_all.size();
+  ci_start[pL] = c->ci_all.size();
+  const int T = 1 << (c->L - 1);
+  for (int t = 1; t <= T; ++t) {
+    int lmin = c->L - 1;
+    for (int l = 0; l < c->L; ++l)
+      if (t % (1 << (c->L - 1 - l)) == 0) {
+        lmin = l;
+        break;
+      }
+    Tick tk;
+    tk.lmin = lmin;
+    tk.sc_off = c->sc_all.size();
+    for (int l = lmin; l < c->L; ++l) {
+      const auto &v = (l == lmin && l > 0) ? c->lev[l].items1 : c->lev[l].items2;
+      c->sc_all.insert(c->sc_all.end(), v.begin(), v.end());
+    }
+    tk.sc_n = c->sc_all.size() - tk.sc_off;
+    tk.gp_off = gp_start[std::min(lmin, pL)];
+    tk.gp_n = gp_start[pL] - tk.gp_off;
+    tk.ci_off = ci_start[std::min(lmin, pL)];
+    tk.ci_n = ci_start[pL] - tk.ci_off;
+    c->ticks.push_back(tk);
+  }
+  c->red_items.clear();
+  for (int l = 0; l < c->L; ++l)
+    for (int32_t b = 0; b < c->lev[l].nb; ++b) {
+      WorkItem w;
+      w.brick = b;
+      w.level = (uint8_t)l;
+      w.thr = 0;
+      w.drag = 0;
+      w.pad = 0;
+      c->red_items.push_back(w);
+    }
+}
+
+size_t store_bytes(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
+size_t comp_bytes(int st) { return st == ST_F64 ? 8 : 4; }
+
+void build_layout(elbm_ctx *c) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  const size_t sb = store_bytes(c->storage);
+  for (int l = 0; l < c->L; ++l) {
+    Level &L = c->lev[l];
+    const size_t nb = (size_t)L.nb;
+    L.o_pop[0] = take(nb * c->Q * BN * sb);
+    L.o_pop[1] = take(nb * c->Q * BN * sb);
+    L.o_cls = take(nb * BN);
+    L.o_mask = take(nb * BN * 4);
+    L.o_w = take(nb * BN * 4);
+    L.o_nbr = take(nb * 27 * 4);
+    L.o_force = take(nb * c->D * BN * 4);
+    L.o_gamma = take(nb * BN * 4);
+    L.o_drag = take(nb * 3 * 8);
+    L.o_borg = take(nb * 3 * 4);
+  }
+  c->o_levstatic = take(sizeof(LevelStatic) * MAXL);
+  c->o_pairstatic = take(sizeof(PairStatic) * MAXL);
+  c->o_sc = take(c->sc_all.size() * sizeof(WorkItem));
+  c->o_gp = take(c->gp_all.size() * sizeof(GPoint));
+  c->o_ci = take(c->ci_all.size() * sizeof(CItem));
+  c->o_sten = take(c->sten.size() * sizeof(StencilEntry));
+  c->o_stage = take((size_t)stage_row_width(c->D) * std::max(c->stage_cols, 1) * comp_bytes(c->storage));
+  c->o_redit = take(c->red_items.size() * sizeof(WorkItem));
+  c->o_part = take(c->red_items.size() * 5 * 8);
+  c->o_res = take(8 * 8);
+  c->tmp_bytes = 1 << 20;
+  c->o_tmp = take(c->tmp_bytes);
+  c->ws_need = off;
+}
+
+LevelStatic level_static(const elbm_ctx *c, int l) {
+  const Level &L = c->lev[l];
+  LevelStatic s;
+  memset(&s, 0, sizeof(s));
+  char *ws = c->ws;
+  s.cls = (const uint8_t *)(ws + L.o_cls);
+  s.mask = (const uint32_t *)(ws + L.o_mask);
+  s.nbr = (const int32_t *)(ws + L.o_nbr);
+  s.weight = (const float *)(ws + L.o_w);
+  s.force = L.force_on ? (const float *)(ws + L.o_force) : nullptr;
+  s.gamma = c->gamma_on ? (float *)(ws + L.o_gamma) : nullptr;
+  s.drag = (double *)(ws + L.o_drag);
+  s.beta = L.beta;
+  const double sc = std::ldexp(1.0, -l);
+  for (int a = 0; a < 3; ++a) s.F[a] = c->Fu[a] * sc;  // du_f = du_c / r (Sec. III.A)
+  s.fscale = sc;
+  int inlet = -1, outflow = -1;
+  for (int f = 0; f < 6; ++f) {
+    if (c->face_kind[f] == ELBM_FACE_INLET) inlet = f;
+    if (c->face_kind[f] == ELBM_FACE_OUTFLOW) outflow = f;
+  }
+  if (inlet >= 0) heq_host(c->D, c->face_u[inlet], s.hin);
+  if (outflow >= 0) s.oshift[outflow / 2] = (outflow & 1) ? 1 : -1;
+  s.nbricks = L.nb;
+  return s;
+}
+
+elbm_status upload_static(elbm_ctx *c) {
+  LevelStatic ls[MAXL];
+  memset(ls, 0, sizeof(ls));
+  for (int l = 0; l < c->L; ++l) ls[l] = level_static(c, l);
+  HIPCK(c, hipMemcpy(c->ws + c->o_levstatic, ls, sizeof(ls), hipMemcpyHostToDevice));
+  PairStatic ps[MAXL];
+  memset(ps, 0, sizeof(ps));
+  for (size_t p = 0; p < c->pairs.size(); ++p) {
+    ps[p].fac_pc = c->pairs[p].fac_pc;
+    ps[p].fac_cp = c->pairs[p].fac_cp;
+    ps[p].parent = (int)p;
+  }
+  HIPCK(c, hipMemcpy(c->ws + c->o_pairstatic, ps, sizeof(ps), hipMemcpyHostToDevice));
+  return ELBM_OK;
+}
+
+void invalidate_graphs(elbm_ctx *c) {
+  for (int p = 0; p < 2; ++p)
+    if (c->graph[p]) {
+      hipGraphExecDestroy(c->graph[p]);
+      c->graph[p] = nullptr;
+    }
+  c->graph_valid = false;
+}
+
+// buffer index of level l at its k-th step (1-based) of a coarse step with level-0 parity p
+int src_index(int l, int p, int k) { return ((l == 0 ? p : 0) ^ ((k - 1) & 1)); }
+
+elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_t side, bool fork) {
+  const Tick &tk = c->ticks[t - 1];
+  void *src[MAXL] = {}, *dst[MAXL] = {};
+  for (int l = tk.lmin; l < c->L; ++l) {
+    const int k = t >> (c->L - 1 - l);
+    const int si = src_index(l, p, k);
+    src[l] = c->ws + c->lev[l].o_pop[si];
+    dst[l] = c->ws + c->lev[l].o_pop[si ^ 1];
+  }
+  const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
+  const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
+  const bool coupling = tk.ci_n > 0;
+  hipStream_t cs = main;
+  if (coupling && fork) {
+    hipEvent_t ef = c->ev_fork[(t - 1) % 64], ej = c->ev_join[(t - 1) % 64];
+    HIPCK(c, hipEventRecord(ef, main));
+    HIPCK(c, hipStreamWaitEvent(side, ef, 0));
+    cs = side;
+    (void)ej;
+  }
+  if (coupling) {
+    GatherArgs g;
+    g.pts = (const GPoint *)(c->ws + c->o_gp) + tk.gp_off;
+    g.n = (int)tk.gp_n;
+    g.stride = stage_row_width(c->D);
+    g.stage = c->ws + c->o_stage;
+    g.lev = lev;
+    g.pairs = pairs;
+    for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
+    LCK(c, launch_gather(c->D, c->storage, g, cs));
+    CoupleArgs a;
+    a.items = (const CItem *)(c->ws + c->o_ci) + tk.ci_off;
+    a.n = (int)tk.ci_n;
+    a.stride = stage_row_width(c->D);
+    a.sten = (const StencilEntry *)(c->ws + c->o_sten);
+    a.stage = c->ws + c->o_stage;
+    a.lev = lev;
+    a.pairs = pairs;
+    for (int l = 0; l < MAXL; ++l) {
+      a.src[l] = src[l];
+      a.dst[l] = dst[l];
+    }
+    LCK(c, launch_couple(c->D, c->storage, a, cs));
+  }
+  SCArgs s;
+  s.items = (const WorkItem *)(c->ws + c->o_sc) + tk.sc_off;
+  s.n_items = (int)tk.sc_n;
+  s.remap = c->xcd_remap;
+  s.lev = lev;
+  for (int l = 0; l < MAXL; ++l) {
+    s.src[l] = src[l];
+    s.dst[l] = dst[l];
+  }
+  LaunchCfg cfg;
+  cfg.threads = c->threads;
+  cfg.occ = c->occ;
+  cfg.grid = c->wg_per_cu > 0 ? std::min<int>((int)tk.sc_n, c->wg_per_cu * c->cu_count) : (int)tk.sc_n;
+  if (c->timing) {
+    hipEvent_t e0, e1;
+    HIPCK(c, hipEventCreate(&e0));
+    HIPCK(c, hipEventCreate(&e1));
+    HIPCK(c, hipEventRecord(e0, main));
+    LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
+    HIPCK(c, hipEventRecord(e1, main));
+    c->tev.push_back(e0);
+    c->tev.push_back(e1);
+  } else {
+    LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
+  }
+  if (coupling && fork) {
+    hipEvent_t ej = c->ev_join[(t - 1) % 64];
+    HIPCK(c, hipEventRecord(ej, side));
+    HIPCK(c, hipStreamWaitEvent(main, ej, 0));
+  }
+  return ELBM_OK;
+}
+
+elbm_status enqueue_coarse_step(elbm_ctx *c, int p, hipStream_t main, hipStream_t side, bool fork) {
+  const int T = 1 << (c->L - 1);
+  for (int t = 1; t <= T; ++t) {
+    elbm_status s = enqueue_tick(c, t, p, main, side, fork);
+    if (s) return s;
+  }
+  return ELBM_OK;
+}
+
+elbm_status build_graphs(elbm_ctx *c) {
+  invalidate_graphs(c);
+  for (int p = 0; p < 2; ++p) {
+    HIPCK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    elbm_status s = enqueue_coarse_step(c, p, c->cap, c->side, true);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (s) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  c->graph_valid = true;
+  return ELBM_OK;
+}
+
+elbm_status check_level(const elbm_ctx *c, int level) {
+  if (!c->finalized) return ELBM_ESTATE;
+  if (level < 0 || level >= c->L) return ELBM_EINVAL;
+  return ELBM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *elbm_status_string(elbm_status s) {
+  switch (s) {
+    case ELBM_OK: return "ok";
+    case ELBM_EINVAL: return "invalid argument or geometry";
+    case ELBM_ESTATE: return "call out of order";
+    case ELBM_ESMALL: return "workspace too small";
+    case ELBM_EDEVICE: return "HIP runtime error";
+    case ELBM_EUNSTABLE: return "unstable state";
+    case ELBM_ENOMEM: return "out of host memory";
+  }
+  return "unknown status";
+}
+
+const char *elbm_last_error(const elbm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+elbm_status elbm_create(const elbm_desc *d, elbm_ctx **out) {
+  if (!d || !out) return ELBM_EINVAL;
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return ELBM_EINVAL;
+  if (d->storage < ST_F64 || d->storage > ST_BF16S) return ELBM_EINVAL;
+  if (d->n_levels < 1 || d->n_levels > MAXL) return ELBM_EINVAL;
+  if (!(d->nu0 > 0)) return ELBM_EINVAL;
+  elbm_ctx *c = new (std::nothrow) elbm_ctx();
+  if (!c) return ELBM_ENOMEM;
+  c->D = d->dim;
+  c->Q = d->dim == 2 ? 9 : 27;
+  c->L = d->n_levels;
+  c->storage = d->storage;
+  c->nu0 = d->nu0;
+  for (int a = 0; a < 3; ++a) {
+    c->N[a] = a < c->D ? d->extent[a] : 1;
+    c->periodic[a] = a < c->D ? (d->periodic[a] != 0) : 0;
+    if (a < c->D && c->N[a] < 2) {
+      delete c;
+      return ELBM_EINVAL;
+    }
+  }
+  for (int f = 0; f < 6; ++f) c->face_kind[f] = (f / 2 < c->D && !c->periodic[f / 2]) ? ELBM_FACE_WALL : 0;
+  *out = c;
+  return ELBM_OK;
+}
+
+elbm_status elbm_destroy(elbm_ctx *c) {
+  if (!c) return ELBM_EINVAL;
+  invalidate_graphs(c);
+  for (hipEvent_t e : c->tev) hipEventDestroy(e);
+  for (int i = 0; i < c->n_events; ++i) {
+    hipEventDestroy(c->ev_fork[i]);
+    hipEventDestroy(c->ev_join[i]);
+  }
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_face(elbm_ctx *c, int face, int kind, const double u[3]) {
+  if (!c) return ELBM_EINVAL;
+  if (c->finalized) FAIL(c, ELBM_ESTATE, "set_face after finalize");
+  if (face < 0 || face >= 6 || face / 2 >= c->D) FAIL(c, ELBM_EINVAL, "bad face %d", face);
+  if (c->periodic[face / 2]) FAIL(c, ELBM_EINVAL, "face %d is on a periodic axis", face);
+  if (kind < ELBM_FACE_WALL || kind > ELBM_FACE_OUTFLOW) FAIL(c, ELBM_EINVAL, "bad face kind %d", kind);
+  for (int f = 0; f < 6; ++f)
+    if (f != face && kind != ELBM_FACE_WALL && c->face_kind[f] == kind)
+      FAIL(c, ELBM_EINVAL, "only one inlet and one outflow face are supported");
+  c->face_kind[face] = kind;
+  for (int a = 0; a < 3; ++a) c->face_u[face][a] = u ? u[a] : 0.0;
+  return ELBM_OK;
+}
+
+elbm_status elbm_add_block(elbm_ctx *c, int level, const int64_t lo[3], const int64_t hi[3]) {
+  if (!c || !lo || !hi) return ELBM_EINVAL;
+  if (c->finalized) FAIL(c, ELBM_ESTATE, "add_block after finalize");
+  if (level < 1 || level >= c->L) FAIL(c, ELBM_EINVAL, "blocks are added to levels 1..%d", c->L - 1);
+  Box b;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = a < c->D ? lo[a] : 0;
+    b.hi[a] = a < c->D ? hi[a] : 0;
+  }
+  for (int a = 0; a < c->D; ++a) {
+    if (b.hi[a] < b.lo[a]) FAIL(c, ELBM_EINVAL, "empty block on axis %d", a);
+    if (c->periodic[a]) {
+      const int64_t P = period(c, level, a);
+      if (b.lo[a] < 0 || b.lo[a] >= P || b.hi[a] - b.lo[a] > P - 1)
+        FAIL(c, ELBM_EINVAL, "block outside the periodic range on axis %d", a);
+      if (b.hi[a] - b.lo[a] == P - 1) continue;
+    } else if (b.lo[a] < 0 || b.hi[a] > extent(c, level, a) - 1) {
+      FAIL(c, ELBM_EINVAL, "block outside the domain on axis %d", a);
+    }
+    if ((b.lo[a] & 1) || (b.hi[a] & 1))
+      FAIL(c, ELBM_EINVAL, "block faces must lie on parent nodes (even coordinates), axis %d", a);
+    if (b.hi[a] - b.lo[a] < 8) FAIL(c, ELBM_EINVAL, "block narrower than 4 parent spacings on axis %d", a);
+  }
+  c->lev[level].boxes.push_back(b);
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_solid(elbm_ctx *c, int level, const int64_t lo[3], const int64_t n[3], const uint8_t *mask) {
+  if (!c || !lo || !n || !mask) return ELBM_EINVAL;
+  if (c->finalized) FAIL(c, ELBM_ESTATE, "set_solid after finalize");
+  if (level < 0 || level >= c->L) FAIL(c, ELBM_EINVAL, "bad level %d", level);
+  SolidSpec s;
+  size_t tot = 1;
+  for (int a = 0; a < 3; ++a) {
+    s.lo[a] = a < c->D ? lo[a] : 0;
+    s.n[a] = a < c->D ? n[a] : 1;
+    if (s.n[a] < 1) FAIL(c, ELBM_EINVAL, "bad solid extent");
+    tot *= (size_t)s.n[a];
+  }
+  s.mask.assign(mask, mask + tot);
+  c->lev[level].solids.push_back(std::move(s));
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_force_uniform(elbm_ctx *c, const double F[3]) {
+  if (!c || !F) return ELBM_EINVAL;
+  for (int a = 0; a < 3; ++a) c->Fu[a] = a < c->D ? F[a] : 0.0;
+  if (c->bound) {
+    elbm_status s = upload_static(c);
+    if (s) return s;
+    invalidate_graphs(c);
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_finalize(elbm_ctx *c, size_t *ws_bytes) {
+  if (!c) return ELBM_EINVAL;
+  if (c->finalized) FAIL(c, ELBM_ESTATE, "finalize twice");
+  for (int l = 1; l < c->L; ++l)
+    if (c->lev[l].boxes.empty()) FAIL(c, ELBM_EINVAL, "level %d has no blocks", l);
+  try {
+    for (int l = 0; l < c->L; ++l) {
+      elbm_status s = build_level_geometry(c, l);
+      if (s) return s;
+    }
+    for (int l = 0; l < c->L; ++l) {
+      elbm_status s = build_level_links(c, l);
+      if (s) return s;
+    }
+    // a parent ring node must not lie on the parent's own interface layers
+    for (int l = 0; l < c->L; ++l) {
+      const Level &L = c->lev[l];
+      for (size_t k = 0; k < L.exists.size(); ++k)
+        if (L.exists[k] && L.ring[k] && L.pd[k] < 2)
+          FAIL(c, ELBM_EINVAL, "level %d: a ring node lies on the level's own interface (nesting margin)", l);
+    }
+    elbm_status s = build_pairs(c);
+    if (s) return s;
+    build_schedule(c);
+    for (int l = 0; l < c->L; ++l)
+      if ((double)c->lev[l].nb * c->Q * BN * store_bytes(c->storage) >= 4294967296.0)
+        FAIL(c, ELBM_EINVAL, "level %d population buffer exceeds 4 GiB (32-bit offsets)", l);
+    build_layout(c);
+  } catch (const std::bad_alloc &) {
+    FAIL(c, ELBM_ENOMEM, "host allocation failed in finalize");
+  }
+  c->finalized = true;
+  if (ws_bytes) *ws_bytes = c->ws_need;
+  return ELBM_OK;
+}
+
+elbm_status elbm_level_box(const elbm_ctx *c, int level, int64_t lo[3], int64_t n[3]) {
+  if (!c || !lo || !n) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = c->lev[level].blo[a];
+    n[a] = c->lev[level].bn[a];
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_level_info(const elbm_ctx *c, int level, int64_t *n_nodes, int64_t *n_fluid, double *beta,
+                            int64_t *n_bricks) {
+  if (!c) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  const Level &L = c->lev[level];
+  if (n_nodes) *n_nodes = L.n_nodes;
+  if (n_fluid) *n_fluid = L.n_fluid;
+  if (beta) *beta = L.beta;
+  if (n_bricks) *n_bricks = L.nb;
+  return ELBM_OK;
+}
+
+static void dense_index(const elbm_ctx *c, int level, int32_t b, int n, int64_t &k, bool &in) {
+  const Level &L = c->lev[level];
+  int64_t loc[3] = {n % bdim(c->D, 0), (n / bdim(c->D, 0)) % bdim(c->D, 1), n / (bdim(c->D, 0) * bdim(c->D, 1))};
+  int64_t X = L.borg[3 * b] + loc[0], Y = L.borg[3 * b + 1] + loc[1], Z = L.borg[3 * b + 2] + loc[2];
+  in = X < L.bn[0] && Y < L.bn[1] && Z < L.bn[2];
+  k = X + L.bn[0] * (Y + L.bn[1] * Z);
+}
+
+elbm_status elbm_node_class(const elbm_ctx *c, int level, int32_t *out) {
+  if (!c || !out) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  const Level &L = c->lev[level];
+  const int64_t tot = L.bn[0] * L.bn[1] * L.bn[2];
+  for (int64_t k = 0; k < tot; ++k) out[k] = -1;
+  for (int32_t b = 0; b < L.nb; ++b)
+    for (int n = 0; n < BN; ++n) {
+      const size_t q = (size_t)b * BN + n;
+      if (!L.exists[q]) continue;
+      int64_t k;
+      bool in;
+      dense_index(c, level, b, n, k, in);
+      if (!in) continue;
+      out[k] = (int32_t)(L.solid[q] | (L.ring[q] << 1) | (std::min<int>(L.pd[q], 3) << 2));
+    }
+  return ELBM_OK;
+}
+
+elbm_status elbm_weights(const elbm_ctx *c, int level, double *out) {
+  if (!c || !out) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  const Level &L = c->lev[level];
+  const int64_t tot = L.bn[0] * L.bn[1] * L.bn[2];
+  for (int64_t k = 0; k < tot; ++k) out[k] = 0.0;
+  for (int32_t b = 0; b < L.nb; ++b)
+    for (int n = 0; n < BN; ++n) {
+      const size_t q = (size_t)b * BN + n;
+      if (!L.exists[q]) continue;
+      int64_t k;
+      bool in;
+      dense_index(c, level, b, n, k, in);
+      if (in) out[k] = L.weight[q];
+    }
+  return ELBM_OK;
+}
+
+elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
+  if (!c || !ws) return ELBM_EINVAL;
+  if (!c->finalized) FAIL(c, ELBM_ESTATE, "bind before finalize");
+  if (bytes < c->ws_need) FAIL(c, ELBM_ESMALL, "workspace %zu bytes < %zu required", bytes, c->ws_need);
+  if ((uintptr_t)ws & 255) FAIL(c, ELBM_EINVAL, "workspace must be 256-byte aligned");
+  invalidate_graphs(c);
+  c->ws = (char *)ws;
+  c->stream = (hipStream_t)stream;
+  int dev = 0;
+  HIPCK(c, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCK(c, hipGetDeviceProperties(&prop, dev));
+  c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (!c->side) HIPCK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  if (!c->cap) HIPCK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->n_events) {
+    for (int i = 0; i < 64; ++i) {
+      HIPCK(c, hipEventCreateWithFlags(&c->ev_fork[i], hipEventDisableTiming));
+      HIPCK(c, hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming));
+    }
+    c->n_events = 64;
+  }
+  for (int l = 0; l < c->L; ++l) {
+    Level &L = c->lev[l];
+    HIPCK(c, hipMemcpy(c->ws + L.o_cls, L.cls.data(), L.cls.size(), hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(c->ws + L.o_mask, L.mask.data(), L.mask.size() * 4, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(c->ws + L.o_w, L.weight.data(), L.weight.size() * 4, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(c->ws + L.o_nbr, L.nbr.data(), L.nbr.size() * 4, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemcpy(c->ws + L.o_borg, L.borg.data(), L.borg.size() * 4, hipMemcpyHostToDevice));
+    HIPCK(c, hipMemset(c->ws + L.o_drag, 0, (size_t)L.nb * 3 * 8));
+    HIPCK(c, hipMemset(c->ws + L.o_gamma, 0, (size_t)L.nb * BN * 4));
+    const size_t pb = (size_t)L.nb * c->Q * BN * store_bytes(c->storage);
+    HIPCK(c, hipMemset(c->ws + L.o_pop[0], 0, pb));
+    HIPCK(c, hipMemset(c->ws + L.o_pop[1], 0, pb));
+    c->drag_steps[l] = 0;
+  }
+  if (!c->sc_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_sc, c->sc_all.data(), c->sc_all.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  if (!c->gp_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_gp, c->gp_all.data(), c->gp_all.size() * sizeof(GPoint), hipMemcpyHostToDevice));
+  if (!c->ci_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_ci, c->ci_all.data(), c->ci_all.size() * sizeof(CItem), hipMemcpyHostToDevice));
+  if (!c->sten.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_sten, c->sten.data(), c->sten.size() * sizeof(StencilEntry),
+                       hipMemcpyHostToDevice));
+  if (!c->red_items.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_redit, c->red_items.data(), c->red_items.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice));
+  c->parity = 0;
+  c->bound = true;
+  elbm_status s = upload_static(c);
+  if (s) return s;
+  HIPCK(c, hipDeviceSynchronize());
+  return ELBM_OK;
+}
+
+elbm_status elbm_init_fields(elbm_ctx *c, int level, const double *rho, const double *u, const double *noise) {
+  if (!c || !rho || !u) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "init before bind");
+  const Level &L = c->lev[level];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  const size_t nb = tot * (1 + c->D + (noise ? c->Q : 0)) * sizeof(double);
+  double *d = nullptr;
+  HIPCK(c, hipMalloc((void **)&d, nb));
+  hipError_t e = hipMemcpy(d, rho, tot * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + tot, u, tot * c->D * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && noise) e = hipMemcpy(d + tot * (1 + c->D), noise, tot * c->Q * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    FAIL(c, ELBM_EDEVICE, "upload: %s", hipGetErrorString(e));
+  }
+  const int cur = level == 0 ? c->parity : 0;
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  int rc = launch_init(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
+                       L.nb, (const int32_t *)(c->ws + L.o_borg), box, d, d + tot,
+                       noise ? d + tot * (1 + c->D) : nullptr, c->stream);
+  e = hipStreamSynchronize(c->stream);
+  hipFree(d);
+  if (rc) FAIL(c, ELBM_EDEVICE, "init kernel: %s", hipGetErrorString((hipError_t)rc));
+  if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "init: %s", hipGetErrorString(e));
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_force_field(elbm_ctx *c, int level, const double *F) {
+  if (!c) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "set_force_field before bind");
+  Level &L = c->lev[level];
+  const bool was = L.force_on;
+  if (F) {
+    Dims box;
+    for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+    LCK(c, launch_force_scatter(c->D, (float *)(c->ws + L.o_force), F, L.nb, (const int32_t *)(c->ws + L.o_borg),
+                                box, c->stream));
+    L.force_on = true;
+  } else {
+    L.force_on = false;
+  }
+  if (was != L.force_on) {
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    s = upload_static(c);
+    if (s) return s;
+    invalidate_graphs(c);
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_advance(elbm_ctx *c, int n) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "advance before bind");
+  if (n < 0) FAIL(c, ELBM_EINVAL, "negative step count");
+  if (c->use_graph && !c->timing && !c->graph_valid) {
+    elbm_status s = build_graphs(c);
+    if (s) return s;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (c->use_graph && !c->timing) {
+      HIPCK(c, hipGraphLaunch(c->graph[c->parity], c->stream));
+    } else {
+      elbm_status s = enqueue_coarse_step(c, c->parity, c->stream, c->side, false);
+      if (s) return s;
+    }
+    c->parity ^= 1;
+    for (int l = 0; l < c->L; ++l) c->drag_steps[l] += (int64_t)1 << l;
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_read_moments(elbm_ctx *c, int level, double *rho, double *u, double *gamma) {
+  if (!c) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "read before bind");
+  const Level &L = c->lev[level];
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  if (rho) LCK(c, launch_fill_nan(rho, tot, c->stream));
+  if (u) LCK(c, launch_fill_nan(u, tot * c->D, c->stream));
+  if (gamma) LCK(c, launch_fill_nan(gamma, tot, c->stream));
+  const int cur = level == 0 ? c->parity : 0;
+  LCK(c, launch_read(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
+                     L.nb, (const int32_t *)(c->ws + L.o_borg), box, rho, u, gamma, nullptr, c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_read_populations(elbm_ctx *c, int level, double *f) {
+  if (!c || !f) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "read before bind");
+  const Level &L = c->lev[level];
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  LCK(c, launch_fill_nan(f, tot * c->Q, c->stream));
+  const int cur = level == 0 ? c->parity : 0;
+  LCK(c, launch_read(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
+                     L.nb, (const int32_t *)(c->ws + L.o_borg), box, nullptr, nullptr, nullptr, f, c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_sample_populations(elbm_ctx *c, int level, int64_t n, const int64_t *coords, double *out) {
+  if (!c || (n > 0 && (!coords || !out)) || n < 0) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "sample before bind");
+  const Level &L = c->lev[level];
+  const int cur = level == 0 ? c->parity : 0;
+  const int64_t chunk = (int64_t)((c->tmp_bytes - 512) / (8 + 8 * c->Q));
+  std::vector<int32_t> br, nd;
+  for (int64_t s0 = 0; s0 < n; s0 += chunk) {
+    const int64_t m = std::min(chunk, n - s0);
+    br.assign((size_t)m, -1);
+    nd.assign((size_t)m, 0);
+    for (int64_t i = 0; i < m; ++i) {
+      NodeRef r = locate(c, level, coords + 3 * (s0 + i));
+      if (r.brick >= 0 && !L.solid[(size_t)r.brick * BN + r.node]) {
+        br[i] = r.brick;
+        nd[i] = r.node;
+      }
+    }
+    char *tmp = c->ws + c->o_tmp;
+    HIPCK(c, hipMemcpyAsync(tmp, br.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCK(c, hipMemcpyAsync(tmp + m * 4, nd.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    double *dout = (double *)(tmp + align_up(m * 8, 256));
+    LCK(c, launch_sample(c->D, c->storage, c->ws + L.o_pop[cur], nullptr, level, (int)m, (const int32_t *)tmp,
+                         (const int32_t *)(tmp + m * 4), dout, c->stream));
+    HIPCK(c, hipMemcpyAsync(out + s0 * c->Q, dout, m * c->Q * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_reduce(elbm_ctx *c, double *mass, double mom[3], int64_t *n_unstable) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "reduce before bind");
+  void *pops[MAXL] = {};
+  for (int l = 0; l < c->L; ++l) pops[l] = c->ws + c->lev[l].o_pop[l == 0 ? c->parity : 0];
+  LCK(c, launch_reduce(c->D, c->storage, pops, (const LevelStatic *)(c->ws + c->o_levstatic),
+                       (const WorkItem *)(c->ws + c->o_redit), (int)c->red_items.size(), (double *)(c->ws + c->o_part),
+                       (double *)(c->ws + c->o_res), c->stream));
+  double r[5];
+  HIPCK(c, hipMemcpyAsync(r, c->ws + c->o_res, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  double vol = 0;
+  for (int l = 0; l < c->L; ++l)
+    for (float w : c->lev[l].weight) vol += w;
+  if (mass) *mass = vol + r[0];
+  if (mom)
+    for (int a = 0; a < 3; ++a) mom[a] = a < c->D ? r[1 + a] : 0.0;
+  if (n_unstable) *n_unstable = (int64_t)llround(r[4]);
+  return ELBM_OK;
+}
+
+elbm_status elbm_check(elbm_ctx *c) {
+  int64_t bad = 0;
+  double m, j[3];
+  elbm_status s = elbm_reduce(c, &m, j, &bad);
+  if (s) return s;
+  if (bad > 0 || !std::isfinite(m)) FAIL(c, ELBM_EUNSTABLE, "%lld unstable nodes", (long long)bad);
+  return ELBM_OK;
+}
+
+elbm_status elbm_drag(elbm_ctx *c, int level, double F[3], int64_t *steps, int reset) {
+  if (!c || !F) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "drag before bind");
+  const Level &L = c->lev[level];
+  std::vector<double> part((size_t)L.nb * 3);
+  HIPCK(c, hipMemcpyAsync(part.data(), c->ws + L.o_drag, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  double acc[3] = {0, 0, 0};
+  for (int32_t b = 0; b < L.nb; ++b)
+    for (int a = 0; a < 3; ++a) acc[a] += part[(size_t)b * 3 + a];
+  for (int a = 0; a < 3; ++a) F[a] = acc[a];
+  if (steps) *steps = c->drag_steps[level];
+  if (reset) {
+    LCK(c, launch_zero(c->ws + L.o_drag, (size_t)L.nb * 3 * 8, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    c->drag_steps[level] = 0;
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_gamma_output(elbm_ctx *c, int enable) {
+  if (!c) return ELBM_EINVAL;
+  c->gamma_on = enable != 0;
+  if (c->bound) {
+    elbm_status s = upload_static(c);
+    if (s) return s;
+    invalidate_graphs(c);
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_remap, int threads, int occupancy) {
+  if (!c) return ELBM_EINVAL;
+  if (occupancy != 1 && occupancy != 4) FAIL(c, ELBM_EINVAL, "occupancy variant must be 1 or 4");
+  if (threads != 64 && threads != 128 && threads != 256) FAIL(c, ELBM_EINVAL, "threads must be 64, 128 or 256");
+  if (wg_per_cu < 0 || wg_per_cu > 64) FAIL(c, ELBM_EINVAL, "wg_per_cu out of range");
+  c->use_graph = use_graph != 0;
+  c->wg_per_cu = wg_per_cu;
+  c->xcd_remap = xcd_remap != 0;
+  c->threads = threads;
+  c->occ = occupancy;
+  invalidate_graphs(c);
+  return ELBM_OK;
+}
+
+elbm_status elbm_synchronize(elbm_ctx *c) {
+  if (!c) return ELBM_EINVAL;
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_profile(elbm_ctx *c, int steps, double *ms_total, double *ms_sc, int64_t *n_launch) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "profile before bind");
+  for (hipEvent_t e : c->tev) hipEventDestroy(e);
+  c->tev.clear();
+  hipEvent_t a, b;
+  HIPCK(c, hipEventCreate(&a));
+  HIPCK(c, hipEventCreate(&b));
+  c->timing = true;
+  HIPCK(c, hipEventRecord(a, c->stream));
+  elbm_status s = elbm_advance(c, steps);
+  hipError_t e = hipEventRecord(b, c->stream);
+  c->timing = false;
+  if (s) return s;
+  if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "event record: %s", hipGetErrorString(e));
+  HIPCK(c, hipEventSynchronize(b));
+  float tot = 0;
+  HIPCK(c, hipEventElapsedTime(&tot, a, b));
+  double sc = 0;
+  for (size_t i = 0; i + 1 < c->tev.size(); i += 2) {
+    float m = 0;
+    HIPCK(c, hipEventElapsedTime(&m, c->tev[i], c->tev[i + 1]));
+    sc += m;
+  }
+  if (ms_total) *ms_total = tot;
+  if (ms_sc) *ms_sc = sc;
+  if (n_launch) *n_launch = (int64_t)(c->tev.size() / 2);
+  for (hipEvent_t ev : c->tev) hipEventDestroy(ev);
+  c->tev.clear();
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ELBM_OK;
+}
+
+elbm_status elbm_state_bytes(const elbm_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return ELBM_EINVAL;
+  if (!c->finalized) return ELBM_ESTATE;
+  size_t t = 0;
+  for (int l = 0; l < c->L; ++l) t += (size_t)c->lev[l].nb * c->Q * BN * store_bytes(c->storage);
+  *bytes = t;
+  return ELBM_OK;
+}
+
+elbm_status elbm_save_state(elbm_ctx *c, void *dst) {
+  if (!c || !dst) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "save before bind");
+  size_t off = 0;
+  for (int l = 0; l < c->L; ++l) {
+    const Level &L = c->lev[l];
+    const size_t pb = (size_t)L.nb * c->Q * BN * store_bytes(c->storage);
+    LCK(c, launch_copy((char *)dst + off, c->ws + L.o_pop[l == 0 ? c->parity : 0], pb, c->stream));
+    off += pb;
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_load_state(elbm_ctx *c, const void *src) {
+  if (!c || !src) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "load before bind");
+  size_t off = 0;
+  for (int l = 0; l < c->L; ++l) {
+    const Level &L = c->lev[l];
+    const size_t pb = (size_t)L.nb * c->Q * BN * store_bytes(c->storage);
+    LCK(c, launch_copy(c->ws + L.o_pop[l == 0 ? c->parity : 0], (const char *)src + off, pb, c->stream));
+    off += pb;
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
+  if (!c) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "tune before bind");
+  if (steps < 1) steps = 1;
+  // cache key: dimension, storage and bricks per level
+  std::string key = "d" + std::to_string(c->D) + "s" + std::to_string(c->storage);
+  for (int l = 0; l < c->L; ++l) key += "_" + std::to_string(c->lev[l].nb);
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof(line), f)) {
+        char k[256];
+        int g, w, x, t, o;
+        if (sscanf(line, " \"%255[^\"]\": [%d, %d, %d, %d, %d]", k, &g, &w, &x, &t, &o) == 6 && key == k) {
+          fclose(f);
+          return elbm_set_launch(c, g, w, x, t, o);
+        }
+      }
+      fclose(f);
+    }
+  }
+  size_t sb = 0;
+  elbm_state_bytes(c, &sb);
+  void *save = nullptr;
+  HIPCK(c, hipMalloc(&save, sb));
+  elbm_status s = elbm_save_state(c, save);
+  const int par0 = c->parity;
+  struct Cand {
+    int w, x, t, o;
+  };
+  std::vector<Cand> cands;
+  for (int o : {1, 4})
+    for (int w : {0, 2, 4, 8})
+      for (int x : {0, 1})
+        for (int t : {256, 128}) cands.push_back({w, x, t, o});
+  double best = 1e30;
+  Cand bc = {0, 1, 256, 1};
+  hipEvent_t a = nullptr, b = nullptr;
+  if (!s && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    for (const Cand &cd : cands) {
+      if ((s = elbm_set_launch(c, 1, cd.w, cd.x, cd.t, cd.o))) break;
+      if ((s = elbm_advance(c, 1))) break;  // warm-up and graph build
+      hipEventRecord(a, c->stream);
+      if ((s = elbm_advance(c, steps))) break;
+      hipEventRecord(b, c->stream);
+      hipEventSynchronize(b);
+      float ms = 0;
+      hipEventElapsedTime(&ms, a, b);
+      if (ms < best) {
+        best = ms;
+        bc = cd;
+      }
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  // restore the state (parity first, so that the buffers line up)
+  c->parity = par0;
+  if (!s) s = elbm_load_state(c, save);
+  hipStreamSynchronize(c->stream);
+  hipFree(save);
+  if (s) return s;
+  s = elbm_set_launch(c, 1, bc.w, bc.x, bc.t, bc.o);
+  if (s) return s;
+  for (int l = 0; l < c->L; ++l) {  // the timing runs advanced the drag accumulators
+    LCK(c, launch_zero(c->ws + c->lev[l].o_drag, (size_t)c->lev[l].nb * 3 * 8, c->stream));
+    c->drag_steps[l] = 0;
+  }
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "\"%s\": [%d, %d, %d, %d, %d]\n", key.c_str(), 1, bc.w, bc.x, bc.t, bc.o);
+      fclose(f);
+    }
+  }
+  return ELBM_OK;
+}
+
+}  // extern "C"

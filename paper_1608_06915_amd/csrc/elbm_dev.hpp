@@ -1,0 +1,147 @@
+// elbm_dev.hpp -- data layout shared by the host runtime and the HIP kernels.
+//
+// Storage: each level's nodes live in bricks of 16x4x4 (3-D) or 16x16 (2-D) nodes,
+// allocated only where the level has nodes.  Populations are SoA inside a brick:
+// pop[brick][i][node], node = x + BX*(y + BY*z), so a wavefront reads 64 consecutive
+// nodes of one population.  Streaming pulls across brick faces through a 27-entry
+// neighbour table per brick (periodic wrap folded into the table).
+#pragma once
+#include <stdint.h>
+
+namespace elbm {
+
+constexpr int MAXL = 8;
+constexpr int BN = 256;  // nodes per brick (both dimensions)
+
+template <int D> struct Brick;
+template <> struct Brick<2> {
+  static constexpr int BX = 16, BY = 16, BZ = 1, LX = 4, LY = 4;
+};
+template <> struct Brick<3> {
+  static constexpr int BX = 16, BY = 4, BZ = 4, LX = 4, LY = 2;
+};
+
+// node class byte
+enum : uint8_t {
+  CLS_MODE = 0x3,      // 0: not stream-collided, 1: first substep only (inner layer), 2: every step
+  CLS_LINKS = 0x4,     // mask holds bounce-back populations
+  CLS_INLET = 0x8,     // mask holds populations entering through the inlet face
+  CLS_OUTFLOW = 0x10,  // mask holds populations entering through the outflow face
+  CLS_DRAG = 0x20,     // has links to solid nodes (momentum exchange)
+  CLS_FLUID = 0x40,    // node exists and is not solid
+};
+
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
+
+struct WorkItem {  // one brick of one level in a stream-collide launch
+  int32_t brick;
+  uint8_t level;
+  uint8_t thr;    // process nodes with mode >= thr
+  uint8_t drag;   // brick holds drag nodes
+  uint8_t pad;
+};
+
+struct GPoint {  // coarse-aligned interpolation point of an interface (gather phase)
+  int32_t brick;
+  uint16_t node;
+  uint8_t level;  // level the value is read from
+  uint8_t pair;   // interface pair index (parent level)
+  int32_t slot;   // column in the staging buffer
+};
+
+struct CItem {  // node rebuilt by the coupling phase
+  int32_t brick;
+  uint16_t node;
+  uint8_t level;  // level of the node written
+  uint8_t kind;   // 0: fine interface node from stencil, 1: coarse ring node from fine twin
+  int32_t a;      // kind 0: first stencil entry; kind 1: fine brick
+  int32_t b;      // kind 0: stencil entries;     kind 1: fine node
+};
+
+struct StencilEntry {
+  int32_t slot;
+  float w;
+};
+
+struct LevelStatic {  // device-resident per-level constants and table pointers
+  const uint8_t *cls;
+  const uint32_t *mask;
+  const int32_t *nbr;
+  const float *weight;
+  const float *force;  // [brick][D][BN], level-0 units, or null
+  float *gamma;        // [brick][BN] or null
+  double *drag;        // [brick][3]
+  double beta;
+  double F[3];   // uniform force density, level units
+  double fscale; // 2^-l
+  double hin[27];  // inlet populations minus weights
+  int32_t oshift[3];
+  int32_t nbricks;
+};
+
+struct PairStatic {
+  double fac_pc;  // parent non-equilibrium to child scale: beta_c / (2 beta_f)
+  double fac_cp;  // child non-equilibrium to parent scale: 2 beta_f / beta_c
+  int32_t parent;
+  int32_t pad;
+};
+
+struct SCArgs {
+  const WorkItem *items;
+  int32_t n_items;
+  int32_t remap;  // XCD-aware item mapping
+  const LevelStatic *lev;
+  void *src[MAXL];
+  void *dst[MAXL];
+};
+
+struct GatherArgs {
+  const GPoint *pts;
+  int32_t n;
+  int32_t stride;  // staging buffer column count
+  void *stage;     // [1+D+Q][stride] compute type
+  const LevelStatic *lev;
+  const PairStatic *pairs;
+  void *src[MAXL];
+};
+
+struct CoupleArgs {
+  const CItem *items;
+  int32_t n;
+  int32_t stride;
+  const StencilEntry *sten;
+  const void *stage;
+  const LevelStatic *lev;
+  const PairStatic *pairs;
+  void *src[MAXL];
+  void *dst[MAXL];
+};
+
+// host-side launchers (kernels.hip)
+struct LaunchCfg {
+  int grid;
+  int threads;
+  int occ;  // stream-collide register-budget variant: 1 uncapped, 4 capped at 128 VGPRs
+};
+int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *stream);
+int launch_gather(int D, int st, const GatherArgs &a, void *stream);
+int launch_couple(int D, int st, const CoupleArgs &a, void *stream);
+struct Dims {
+  int64_t n[3];
+};
+int launch_init(int D, int st, void *pop, const LevelStatic *lev_dev, int level, int nbricks, const int32_t *borg,
+                Dims box, const double *rho, const double *u, const double *noise, void *stream);
+int launch_read(int D, int st, const void *pop, const LevelStatic *lev_dev, int level, int nbricks,
+                const int32_t *borg, Dims box, double *rho, double *u, double *gamma, double *f, void *stream);
+int launch_fill_nan(double *p, size_t count, void *stream);
+int launch_sample(int D, int st, const void *pop, const LevelStatic *lev_dev, int level, int n,
+                  const int32_t *bricks, const int32_t *nodes, double *out, void *stream);
+int launch_reduce(int D, int st, void *const *pops, const LevelStatic *lev_dev, const WorkItem *items, int n_items,
+                  double *partials, double *result, void *stream);
+int launch_force_scatter(int D, float *force, const double *F, int nbricks, const int32_t *borg, Dims box,
+                         void *stream);
+int stage_row_width(int D);
+int launch_zero(void *p, size_t bytes, void *stream);
+int launch_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+}  // namespace elbm

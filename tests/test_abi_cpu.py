@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol declared in include/elbm.h, validates arguments, and its host geometry
+(node classes, owned-volume weights, index boxes, level parameters) equals the
+oracle's, which is computed by a different algorithm."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06915_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def elbm():
+    from paper_1608_06915_amd import build, elbm as e
+
+    if not os.path.exists(e.LIB_PATH):
+        build.build()
+    e.lib()
+    return e
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "elbm.h")).read()
+    return sorted(set(re.findall(r"\b(elbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(elbm):
+    import ctypes
+
+    L = ctypes.CDLL(elbm.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(elbm.EXPORTS)
+
+
+def test_argument_validation(elbm):
+    lat = elbm.Lattice(2, (32, 32), (True, True), 0.01, 2)
+    with pytest.raises(elbm.ElbmError):
+        lat.add_block(1, (3, 8), (40, 40))  # odd face
+    with pytest.raises(elbm.ElbmError):
+        lat.add_block(0, (8, 8), (40, 40))  # level 0 has no blocks
+    with pytest.raises(elbm.ElbmError):
+        lat.set_face(0, elbm.FACE_INLET)  # periodic axis
+    with pytest.raises(elbm.ElbmError):
+        lat.advance(1)  # before bind
+    lat.add_block(1, (16, 16), (48, 48))
+    lat.finalize()
+    with pytest.raises(elbm.ElbmError):
+        lat.add_block(1, (16, 16), (48, 48))  # after finalize
+
+
+def test_margin_violation_is_reported(elbm):
+    # a 3-level nest whose finest block touches the middle level's interface
+    lat = elbm.Lattice(2, (32, 32), (True, True), 0.01, 3)
+    lat.add_block(1, (16, 16), (48, 48))
+    lat.add_block(2, (34, 34), (60, 60))
+    with pytest.raises(elbm.ElbmError):
+        lat.finalize()
+
+
+def test_brick_alignment_of_periodic_axes(elbm):
+    lat = elbm.Lattice(3, (20, 8, 8), (True, True, True), 0.01, 1)
+    with pytest.raises(elbm.ElbmError):
+        lat.finalize()  # 20 is not a multiple of the 16-node brick
+
+
+CASES = {
+    "tgv": lambda: synth.tgv2d(),
+    "cylinder": lambda: synth.cylinder2d(),
+    "channel": lambda: synth.channel3d(32, 20, 16, 4),
+    "sphere3lvl": lambda: synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)),
+                                         l2=((16, 8, 8), (24, 16, 16)), centre=(20, 12, 12)),
+    "forest4lvl": lambda: synth.forest3d(root=(4, 4, 4), counts=(8, 8, 1), block=8),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_host_geometry_equals_oracle(elbm, case):
+    sp = CASES[case]()
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
+    synth.apply(sp, g)
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
+    synth.apply(sp, o)
+    for l in range(sp.levels):
+        lg, ng = g.level_box(l)
+        lo, no = o.level_box(l)
+        assert lg.tolist() == lo.tolist() and ng.tolist() == no.tolist()
+        assert np.array_equal(g.node_class(l), o.node_class(l))
+        assert np.allclose(g.weights(l), o.weights(l), rtol=0, atol=1e-15)
+        nn, nf, beta, nb = g.level_info(l)
+        onn, onf, obeta = o.level_info(l)
+        assert (nn, nf) == (onn, onf)
+        assert beta == pytest.approx(obeta, rel=1e-15)
+
+
+def test_survey_workload_node_counts(elbm):
+    """Full-size channel: 128x50x64 coarse nodes and two 256x17x128 fine slabs."""
+    sp = synth.channel3d()
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
+    synth.apply(sp, g)
+    assert g.level_info(0)[1] == 128 * 50 * 64
+    assert g.level_info(1)[1] == 2 * 256 * 17 * 128

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle on the
+same seeded inputs.
+
+Tolerances:
+  FP64 storage and arithmetic: populations agree to 1e-13 (rounding-order only).
+  FP32: max |u_gpu - u_oracle| / U <= 1e-5 at short horizons (the target bound).
+  FP16 weight-shifted storage: <= 1e-3; BF16 weight-shifted: reported and bounded
+  by 1e-2 (8-bit mantissa of f - W).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06915_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def elbm():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1608_06915_amd import elbm as e
+
+    e.lib()
+    return e
+
+
+def pair(elbm, sp, storage, steps, gamma=False, launch=None):
+    print("case %s storage=%s levels=%d steps=%d" % (sp.name, storage, sp.levels, steps), flush=True)
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
+    synth.apply(sp, g)
+    synth.apply(sp, o)
+    g.bind()
+    if launch:
+        g.set_launch(**launch)
+    if gamma:
+        g.set_gamma_output(True)
+    for l in range(sp.levels):
+        lo, n = o.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        g.init(l, rho, u, nz)
+        o.init(l, rho, u, nz)
+    if steps:
+        g.advance(steps)
+        o.advance(steps)
+    g.synchronize()
+    return g, o
+
+
+def max_du(g, o, sp):
+    e = 0.0
+    for l in range(sp.levels):
+        _, ug = g.moments(l)
+        _, uo, _ = o.moments(l)
+        m = np.isfinite(uo)
+        assert np.array_equal(m, np.isfinite(ug)), "node sets differ on level %d" % l
+        e = max(e, float(np.max(np.abs(ug[m] - uo[m]))))
+    return e / sp.U
+
+
+def max_df(g, o, sp):
+    e = 0.0
+    for l in range(sp.levels):
+        a, b = g.get_f(l), o.get_f(l)
+        m = np.isfinite(b)
+        assert np.array_equal(m, np.isfinite(a)), "node sets differ on level %d" % l
+        e = max(e, float(np.max(np.abs(a[m] - b[m]))))
+    return e
+
+
+# ----------------------------------------------------------------- FP64: exact parity
+def test_single_node_updates_fp64_3d(elbm):
+    """One step of a periodic D3Q27 box from generic non-equilibrium states."""
+    sp = synth.Spec("box3", 3, (16, 8, 8), (True,) * 3, 0.004, 1)
+
+    def init(level, lo, n):
+        shp = tuple(int(v) for v in n[::-1])
+        r = synth.rng(7)
+        u = r.uniform(-0.08, 0.08, size=(3,) + shp)
+        return 1 + r.uniform(-0.02, 0.02, size=shp), u, synth.pop_noise(27, shp, 0.03, 8)
+
+    sp.init = init
+    g, o = pair(elbm, sp, "f64", 1)
+    assert max_df(g, o, sp) < 1e-15
+
+
+def test_taylor_green_two_level_fp64_full_horizon(elbm):
+    """64^2 Taylor-Green with the [16,48]^2 refined patch, 1000 coarse steps, FP64."""
+    sp = synth.tgv2d()
+    g, o = pair(elbm, sp, "f64", 1000, gamma=True)
+    assert max_df(g, o, sp) < 1e-13
+    assert max_du(g, o, sp) < 1e-12
+    # decay against the closed form in coarse time
+    k = 2 * math.pi / 64
+    ref = math.exp(-2 * 0.01 * k * k * 1000)
+    _, u = g.moments(0)[:2]
+    lo, n = g.level_box(0)
+    X, Y = synth.coords(lo, n, 2)
+    shape = -np.cos(k * X) * np.sin(k * Y)
+    m = np.isfinite(u[0])
+    amp = np.sum(u[0][m] * shape[m]) / np.sum(shape[m] ** 2) / 0.05
+    assert amp == pytest.approx(ref, rel=1e-2)
+
+
+def test_mass_momentum_and_gamma_fp64(elbm):
+    sp = synth.tgv2d(32, (8, 24), 0.04, 0.02, noise=1e-3)
+    g, o = pair(elbm, sp, "f64", 20, gamma=True)
+    mg, jg, bad = g.reduce()
+    mo, jo = o.reduce()
+    assert bad == 0
+    assert mg == pytest.approx(mo, rel=1e-13)
+    assert np.allclose(jg, jo, rtol=0, atol=1e-12)
+    for l in range(sp.levels):
+        _, _, gg = g.moments(l, gamma=True)
+        _, _, go = o.moments(l)
+        m = np.isfinite(go)
+        # gamma is kept in an FP32 buffer
+        assert np.max(np.abs(gg[m] - go[m]) / np.abs(go[m])) < 3e-7
+
+
+@pytest.mark.parametrize("launch", [dict(use_graph=0), dict(use_graph=1, wg_per_cu=2, xcd_remap=1, threads=128),
+                                    dict(use_graph=1, wg_per_cu=0, xcd_remap=0, threads=64),
+                                    dict(use_graph=1, wg_per_cu=4, xcd_remap=1, threads=256, occupancy=4)],
+                         ids=["eager", "persistent-xcd", "oneperbrick", "regcap"])
+def test_launch_configurations_bitwise_equal(elbm, launch):
+    sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g0, o = pair(elbm, sp, "f32", 6)
+    g1, _ = pair(elbm, sp, "f32", 6, launch=launch)
+    for l in range(sp.levels):
+        assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
+
+
+# ----------------------------------------------------------------- FP32 workloads
+def test_channel_two_level_fp32(elbm):
+    sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g, o = pair(elbm, sp, "f32", 30)
+    assert max_du(g, o, sp) < 1e-5
+    mg, jg, bad = g.reduce()
+    mo, jo = o.reduce()
+    assert bad == 0
+    assert abs(mg - mo) / mo < 1e-6
+
+
+def test_sphere_three_level_inlet_outflow_drag_fp32(elbm):
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12))
+    g, o = pair(elbm, sp, "f32", 20)
+    assert max_du(g, o, sp) < 1e-5
+    Fg, sg = g.drag(2)
+    Fo, so = o.drag(2)
+    assert sg == so == 80
+    # momentum-exchange sums: FP32 populations, FP64 accumulation
+    assert np.allclose(Fg, Fo, rtol=1e-5, atol=2e-6)
+
+
+def test_forest_four_level_fp32(elbm):
+    sp = synth.forest3d(root=(4, 4, 4), counts=(8, 8, 1), block=8)
+    g, o = pair(elbm, sp, "f32", 4)
+    assert max_du(g, o, sp) < 1e-5
+
+
+def test_cylinder_two_level_force_field_drag_fp32(elbm):
+    import torch
+
+    sp = synth.cylinder2d(64, 32, ((10, 8), (30, 24)), (20, 16), 8.0)
+    g, o = pair(elbm, sp, "f32", 0)
+    for l in range(sp.levels):
+        lo, n = o.level_box(l)
+        F = synth.rng(99 + l).uniform(-1e-6, 1e-6, size=(2,) + o.shape(l))
+        o.set_force_field(l, F)
+        g.set_force_field(l, torch.from_numpy(F).cuda())
+    g.advance(40)
+    o.advance(40)
+    assert max_du(g, o, sp) < 1e-5
+    Fg, _ = g.drag(1)
+    Fo, _ = o.drag(1)
+    assert np.allclose(Fg, Fo, rtol=1e-4, atol=2e-6)
+
+
+# ----------------------------------------------------------------- shifted half storage
+# FP16 keeps 11 significant bits of f - W ~ 3 u W: max-norm velocity errors of a few
+# 1e-4 .. 2e-3 of U at U = 0.05 are the quantisation itself; BF16 keeps 8 bits.
+@pytest.mark.parametrize("storage,bound", [("f16s", 3e-3), ("bf16s", 3e-2)])
+def test_channel_half_storage(elbm, storage, bound):
+    sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g, o = pair(elbm, sp, storage, 30)
+    err = max_du(g, o, sp)
+    print("%s max|du|/U = %.3e" % (storage, err))
+    assert err < bound
+
+
+def test_deterministic_repeat(elbm):
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12))
+    a, _ = pair(elbm, sp, "f32", 5)
+    b, _ = pair(elbm, sp, "f32", 5)
+    for l in range(sp.levels):
+        assert np.array_equal(a.get_f(l), b.get_f(l), equal_nan=True)
+    ra, rb = a.reduce(), b.reduce()
+    assert ra[0] == rb[0] and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2]
