@@ -74,6 +74,17 @@ def lib():
         L.ora_kbc.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
         L.ora_beta.restype = ctypes.c_double
         L.ora_beta.argtypes = [ctypes.c_double]
+        L.ora_kbc_adj.restype = None
+        L.ora_kbc_adj.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
+        for name, args in [
+            ("ora_adjoint_run", [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]),
+            ("ora_adjoint_state", [P, ctypes.c_int, dp]),
+            ("ora_adjoint_force", [P, ctypes.c_int, dp]),
+            ("ora_init_adjoint_u", [ctypes.c_int, ctypes.c_int64, dp, dp, dp, dp, dp]),
+        ]:
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = args
         _lib = L
     return _lib
 
@@ -117,6 +128,28 @@ def kbc(D: int, beta_: float, f, F=(0.0, 0.0, 0.0)):
     FF = _f3(F)
     g = lib().ora_kbc(D, float(beta_), _dp(f), _dp(FF), _dp(out), _dp(ds), _dp(dh))
     return out, g, ds, dh
+
+
+def kbc_adj(D: int, beta_: float, f, lo, F=(0.0, 0.0, 0.0)):
+    """Reverse of one collision: (adjoint of f, adjoint of F) for the adjoint lo of f'."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    lf = np.empty(q_of(D))
+    FF = _f3(F)
+    lF = np.zeros(3)
+    lib().ora_kbc_adj(D, float(beta_), _dp(f), _dp(FF), _dp(lo), _dp(lf), _dp(lF))
+    return lf, lF[:D]
+
+
+def init_adjoint_u(D, rho, u, noise, lam):
+    """Gradient wrt the initial velocity through f = f^eq(rho, u)(1 + noise)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().ora_init_adjoint_u(D, rho.size, _dp(rho), _dp(u), None if nz is None else _dp(nz), _dp(lam), _dp(out))
+    return out
 
 
 class OracleError(RuntimeError):
@@ -235,6 +268,26 @@ class Oracle:
         mom = np.zeros(3)
         self._ck(lib().ora_reduce(self._h, ctypes.byref(m), _dp(mom)))
         return m.value, mom[: self.D]
+
+    def adjoint(self, n, objective="drag", body_level=0, direction=(1.0, 0.0, 0.0)):
+        """Run n coarse steps from the current state and the reverse sweep; returns J.
+        objective: "drag" (mean momentum exchange along direction over every
+        collision of body_level) or "ke" (final kinetic energy)."""
+        J = ctypes.c_double()
+        d = _f3(direction)
+        self._ck(lib().ora_adjoint_run(self._h, int(n), 0 if objective == "drag" else 1, int(body_level), _dp(d),
+                                       ctypes.byref(J)))
+        return J.value
+
+    def adjoint_state(self, level):
+        out = np.empty((self.Q,) + self.shape(level))
+        self._ck(lib().ora_adjoint_state(self._h, level, _dp(out)))
+        return out
+
+    def adjoint_force(self, level):
+        out = np.empty((self.D,) + self.shape(level))
+        self._ck(lib().ora_adjoint_force(self._h, level, _dp(out)))
+        return out
 
     def drag(self, level, reset=False):
         F = np.zeros(3)

@@ -84,7 +84,16 @@ typedef struct {
   double beta;
   double drag[3];
   int64_t drag_steps;
+  /* adjoint: of post-collision f, of post-stream g, of the per-node force */
+  double *lf, *lg, *lF;
 } olevel;
+
+/* one recorded operation of a coarse step, with the inputs its reverse needs */
+typedef struct {
+  int op; /* 0 stream, 1 collide, 2 couple */
+  int level, skip;
+  double *g0, *g1;
+} otape;
 
 struct ora {
   int D, Q, L;
@@ -100,6 +109,10 @@ struct ora {
   /* velocity table */
   int c[OMAXQ][3];
   double W[OMAXQ];
+  /* adjoint tape of the coarse step being recorded */
+  int taping;
+  otape *tape;
+  int ntape, captape;
 };
 
 static int fail(ora_t *o, int code, const char *fmt, ...) {
@@ -358,7 +371,15 @@ void ora_destroy(ora_t *o) {
     free(L->force);
     free(L->vf);
     free(L->vg);
+    free(L->lf);
+    free(L->lg);
+    free(L->lF);
   }
+  for (int t = 0; t < o->ntape; ++t) {
+    free(o->tape[t].g0);
+    free(o->tape[t].g1);
+  }
+  free(o->tape);
   free(o);
 }
 
@@ -760,52 +781,91 @@ static void node_force(const ora_t *o, int l, int64_t n, double F[3]) {
  * Boundary readings R9; a source that has no node at this level leaves the
  * population missing (valid bit 0).
  * ------------------------------------------------------------------------- */
-enum { SRC_NODE = 0, SRC_BB = 1, SRC_INLET = 2 };
+enum { SRC_NODE = 0, SRC_BB = 1, SRC_INLET = 2, SRC_NONE = 3 };
+
+/* where population i of node n of level l comes from when streaming: a node m
+ * (SRC_NODE), the node's own opposite population (SRC_BB), the inlet equilibrium
+ * (SRC_INLET, face in *face) or nowhere (SRC_NONE: no node at this level) */
+static int stream_source(const ora_t *o, int l, int64_t n, int i, int64_t *m_out, int *face) {
+  const olevel *L = &o->lev[l];
+  int64_t y[3];
+  int kind = SRC_NODE;
+  for (int a = 0; a < 3; ++a) y[a] = L->pos[3 * n + a] - o->c[i][a];
+  for (int a = 0; a < o->D; ++a) {
+    if (o->periodic[a]) continue;
+    int fc = -1;
+    if (y[a] < 0) fc = 2 * a;
+    else if (y[a] > lv_extent(o, l, a) - 1) fc = 2 * a + 1;
+    if (fc < 0) continue;
+    int fk = o->face_kind[fc];
+    if (fk == ORA_FACE_WALL) kind = SRC_BB;
+    else if (fk == ORA_FACE_INLET && kind != SRC_BB) {
+      kind = SRC_INLET;
+      *face = fc;
+    } else if (fk == ORA_FACE_OUTFLOW) {
+      y[a] += (fc & 1) ? -1 : 1; /* zero-gradient: take the value one node upstream */
+    }
+  }
+  if (kind != SRC_NODE) return kind;
+  if (!canon(o, l, y)) return SRC_NONE;
+  int64_t m = node_id(o, l, y);
+  if (m < 0) return SRC_NONE;
+  if (L->solid[m]) return SRC_BB;
+  *m_out = m;
+  return SRC_NODE;
+}
+
+static double *dup_arr(const double *a, size_t n) {
+  double *b = (double *)malloc(sizeof(double) * (n ? n : 1));
+  memcpy(b, a, sizeof(double) * n);
+  return b;
+}
+static void tape_push(ora_t *o, int op, int l, int skip) {
+  if (!o->taping) return;
+  if (o->ntape == o->captape) {
+    o->captape = o->captape ? 2 * o->captape : 64;
+    o->tape = (otape *)realloc(o->tape, sizeof(otape) * o->captape);
+  }
+  otape *t = &o->tape[o->ntape++];
+  t->op = op;
+  t->level = l;
+  t->skip = skip;
+  t->g0 = t->g1 = NULL;
+  if (op == 1) t->g0 = dup_arr(o->lev[l].g, (size_t)o->lev[l].nn * o->Q);
+  if (op == 2) {
+    t->g0 = dup_arr(o->lev[l].g, (size_t)o->lev[l].nn * o->Q);
+    t->g1 = dup_arr(o->lev[l + 1].g, (size_t)o->lev[l + 1].nn * o->Q);
+  }
+}
+static void tape_clear(ora_t *o) {
+  for (int t = 0; t < o->ntape; ++t) {
+    free(o->tape[t].g0);
+    free(o->tape[t].g1);
+  }
+  o->ntape = 0;
+}
 
 static void stream_level(ora_t *o, int l) {
   olevel *L = &o->lev[l];
   int Q = o->Q;
+  tape_push(o, 0, l, 0);
   for (int64_t n = 0; n < L->nn; ++n) {
     if (L->solid[n]) continue;
     for (int i = 0; i < Q; ++i) {
-      int64_t y[3];
-      int kind = SRC_NODE, out_face = -1;
-      for (int a = 0; a < 3; ++a) y[a] = L->pos[3 * n + a] - o->c[i][a];
-      for (int a = 0; a < o->D; ++a) {
-        if (o->periodic[a]) continue;
-        int face = -1;
-        if (y[a] < 0) face = 2 * a;
-        else if (y[a] > lv_extent(o, l, a) - 1) face = 2 * a + 1;
-        if (face < 0) continue;
-        int fk = o->face_kind[face];
-        if (fk == ORA_FACE_WALL) kind = SRC_BB;
-        else if (fk == ORA_FACE_INLET && kind != SRC_BB) {
-          kind = SRC_INLET;
-          out_face = face;
-        } else if (fk == ORA_FACE_OUTFLOW) {
-          y[a] += (face & 1) ? -1 : 1; /* zero-gradient: take the value one node upstream */
-        }
-      }
+      int64_t m = -1;
+      int face = -1;
+      int kind = stream_source(o, l, n, i, &m, &face);
       double val = NAN;
       uint8_t valid = 0;
       if (kind == SRC_NODE) {
-        if (canon(o, l, y)) {
-          int64_t m = node_id(o, l, y);
-          if (m >= 0) {
-            if (L->solid[m]) kind = SRC_BB;
-            else {
-              val = L->f[(size_t)m * Q + i];
-              valid = L->vf[m];
-            }
-          }
-        }
-      }
-      if (kind == SRC_BB) {
+        val = L->f[(size_t)m * Q + i];
+        valid = L->vf[m];
+      } else if (kind == SRC_BB) {
         val = L->f[(size_t)n * Q + (Q - 1 - i)];
         valid = L->vf[n];
       } else if (kind == SRC_INLET) {
         double feq[OMAXQ];
-        ora_feq(o->D, 1.0, o->face_u[out_face], feq);
+        ora_feq(o->D, 1.0, o->face_u[face], feq);
         val = feq[i];
         valid = 1;
       }
@@ -821,6 +881,7 @@ static void stream_level(ora_t *o, int l) {
 static int collide_level(ora_t *o, int l, int skip_outer) {
   olevel *L = &o->lev[l];
   int Q = o->Q;
+  tape_push(o, 1, l, skip_outer);
   double step_drag[3] = {0, 0, 0};
   for (int64_t n = 0; n < L->nn; ++n) {
     if (L->solid[n]) continue;
@@ -902,6 +963,7 @@ static int point_value(ora_t *o, int lp, const int64_t Xin[3], double *rho, doub
 static int couple(ora_t *o, int lp) {
   olevel *P = &o->lev[lp], *C = &o->lev[lp + 1];
   int Q = o->Q, D = o->D;
+  tape_push(o, 2, lp, 0);
   /* new child interface states, computed from the unmodified post-stream fields */
   double *newc = (double *)malloc(sizeof(double) * (size_t)(C->nn ? C->nn : 1) * Q);
   uint8_t *setc = (uint8_t *)calloc((size_t)(C->nn ? C->nn : 1), 1);
@@ -1099,6 +1161,456 @@ int ora_drag(ora_t *o, int l, double F[3], int64_t *steps, int reset) {
   if (reset) {
     L->drag[0] = L->drag[1] = L->drag[2] = 0.0;
     L->drag_steps = 0;
+  }
+  return 0;
+}
+
+/* ===========================================================================
+ * Discrete adjoint (reverse mode of the exact forward map above, FP64).
+ * The paper has no adjoint; this is the transpose of the linearisation of the
+ * discrete coarse step defined by Sec. II.A and Sec. III.C as implemented here.
+ * At nodes with <dh|dh> = 0 gamma is the constant 2 (reading R3), so dgamma/df = 0.
+ * ========================================================================= */
+
+/* d ln phi / du for the per-axis factor phi(c) = (2 - s) X^c of Eq. feq_iso,
+ * s = sqrt(1 + 3u^2), X = (2u + s)/(1 - u) */
+static double dlnphi(double u, int c) {
+  double s = sqrt(1.0 + 3.0 * u * u), ds = 3.0 * u / s;
+  double d = -ds / (2.0 - s);
+  if (c) d += c * ((2.0 + ds) / (2.0 * u + s) + 1.0 / (1.0 - u));
+  return d;
+}
+
+/* adjoint of f^eq(rho, u): given lam (adjoint of f^eq), accumulate into lrho, lu */
+static void feq_T(int D, double rho, const double u[3], const double *lam, double *lrho, double lu[3]) {
+  int c[OMAXQ][3];
+  double W[OMAXQ], feq[OMAXQ];
+  lattice(D, c, W);
+  ora_feq(D, rho, u, feq);
+  int Q = D == 2 ? 9 : 27;
+  for (int i = 0; i < Q; ++i) {
+    *lrho += lam[i] * feq[i] / rho;
+    for (int a = 0; a < D; ++a) lu[a] += lam[i] * feq[i] * dlnphi(u[a], c[i][a]);
+  }
+}
+
+/* S^T lam for the shear projection S (explicit matrix from unit vectors) */
+static void shear_T(int D, const double *lam, double *out) {
+  int c[OMAXQ][3];
+  double W[OMAXQ];
+  lattice(D, c, W);
+  int Q = D == 2 ? 9 : 27;
+  double e[OMAXQ], col[OMAXQ];
+  for (int j = 0; j < Q; ++j) out[j] = 0.0;
+  for (int j = 0; j < Q; ++j) {
+    for (int k = 0; k < Q; ++k) e[k] = (k == j);
+    shear_part(D, c, e, col); /* column j of S */
+    for (int i = 0; i < Q; ++i) out[j] += col[i] * lam[i];
+  }
+}
+
+/* reverse of ora_kbc: lo = adjoint of f'; returns adjoint of f (overwrites lf) and
+ * adds the adjoint of the force density F to lF */
+void ora_kbc_adj(int D, double beta, const double *f, const double F[3], const double *lo, double *lf,
+                 double lF[3]) {
+  int c[OMAXQ][3];
+  double W[OMAXQ];
+  lattice(D, c, W);
+  int Q = D == 2 ? 9 : 27;
+  double rho = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    for (int a = 0; a < 3; ++a) j[a] += c[i][a] * f[i];
+  }
+  double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  double feq[OMAXQ], d[OMAXQ], ds[OMAXQ], dh[OMAXQ];
+  ora_feq(D, rho, u, feq);
+  for (int i = 0; i < Q; ++i) d[i] = f[i] - feq[i];
+  shear_part(D, c, d, ds);
+  for (int i = 0; i < Q; ++i) dh[i] = d[i] - ds[i];
+  double A = 0, B = 0;
+  for (int i = 0; i < Q; ++i) {
+    A += ds[i] * dh[i] / feq[i];
+    B += dh[i] * dh[i] / feq[i];
+  }
+  double gamma = 2.0;
+  int active = 0;
+  if (B > 0.0) {
+    double g = 1.0 / beta - (2.0 - 1.0 / beta) * A / B;
+    if (isfinite(g)) {
+      gamma = g;
+      active = 1;
+    }
+  }
+  double lds[OMAXQ], ldh[OMAXQ], lfeq[OMAXQ], ld[OMAXQ], tmp[OMAXQ];
+  double lrho = 0, lu[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    lf[i] = lo[i];
+    lds[i] = -2.0 * beta * lo[i];
+    ldh[i] = -beta * gamma * lo[i];
+    lfeq[i] = 0.0;
+  }
+  if (active) {
+    double lg = 0;
+    for (int i = 0; i < Q; ++i) lg += -beta * lo[i] * dh[i];
+    double cc = 2.0 - 1.0 / beta;
+    double lA = -cc / B * lg, lB = cc * A / (B * B) * lg;
+    for (int i = 0; i < Q; ++i) {
+      lds[i] += lA * dh[i] / feq[i];
+      ldh[i] += lA * ds[i] / feq[i] + 2.0 * lB * dh[i] / feq[i];
+      lfeq[i] += -(lA * ds[i] * dh[i] + lB * dh[i] * dh[i]) / (feq[i] * feq[i]);
+    }
+  }
+  for (int i = 0; i < Q; ++i) {
+    ld[i] = ldh[i];
+    lds[i] -= ldh[i];
+  }
+  shear_T(D, lds, tmp);
+  for (int i = 0; i < Q; ++i) ld[i] += tmp[i];
+  for (int i = 0; i < Q; ++i) {
+    lf[i] += ld[i];
+    lfeq[i] -= ld[i];
+  }
+  /* the forcing term vanishes at F = 0 but its derivative does not: always reversed
+   * when the force adjoint is requested */
+  if (F && (lF || F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0)) {
+    double v[3] = {u[0] + F[0] / rho, u[1] + F[1] / rho, u[2] + F[2] / rho};
+    double lv[3] = {0, 0, 0};
+    feq_T(D, rho, v, lo, &lrho, lv);
+    for (int i = 0; i < Q; ++i) lfeq[i] -= lo[i];
+    for (int a = 0; a < D; ++a) {
+      lu[a] += lv[a];
+      lrho -= lv[a] * F[a] / (rho * rho);
+      if (lF) lF[a] += lv[a] / rho;
+    }
+  }
+  feq_T(D, rho, u, lfeq, &lrho, lu);
+  double lj[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) {
+    lj[a] = lu[a] / rho;
+    lrho -= lu[a] * u[a] / rho;
+  }
+  for (int i = 0; i < Q; ++i) {
+    lf[i] += lrho;
+    for (int a = 0; a < D; ++a) lf[i] += c[i][a] * lj[a];
+  }
+}
+
+/* adjoint of (rho, u, fac (g - f^eq(rho, u))) with rho, u the moments of g:
+ * accumulate into lg */
+static void macro_T(const ora_t *o, const double *g, double fac, double lrho, const double lu_in[3],
+                    const double *ln, double *lg) {
+  int Q = o->Q, D = o->D;
+  double rho = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    rho += g[i];
+    for (int a = 0; a < 3; ++a) j[a] += o->c[i][a] * g[i];
+  }
+  double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  double lfeq[OMAXQ] = {0}, lu[3] = {lu_in[0], lu_in[1], lu_in[2]};
+  for (int i = 0; i < Q; ++i) {
+    lg[i] += fac * ln[i];
+    lfeq[i] = -fac * ln[i];
+  }
+  feq_T(D, rho, u, lfeq, &lrho, lu);
+  double lj[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) {
+    lj[a] = lu[a] / rho;
+    lrho -= lu[a] * u[a] / rho;
+  }
+  for (int i = 0; i < Q; ++i) {
+    lg[i] += lrho;
+    for (int a = 0; a < D; ++a) lg[i] += o->c[i][a] * lj[a];
+  }
+}
+
+/* reverse of stream_level: lf[source] += lg, then lg = 0 */
+static void adj_stream(ora_t *o, int l) {
+  olevel *L = &o->lev[l];
+  int Q = o->Q;
+  for (int64_t n = 0; n < L->nn; ++n) {
+    if (L->solid[n]) continue;
+    for (int i = 0; i < Q; ++i) {
+      double v = L->lg[(size_t)n * Q + i];
+      L->lg[(size_t)n * Q + i] = 0.0;
+      if (v == 0.0) continue;
+      int64_t m = -1;
+      int face = -1;
+      int kind = stream_source(o, l, n, i, &m, &face);
+      if (kind == SRC_NODE) L->lf[(size_t)m * Q + i] += v;
+      else if (kind == SRC_BB) L->lf[(size_t)n * Q + (Q - 1 - i)] += v;
+    }
+  }
+}
+
+typedef struct {
+  int objective; /* 0: mean drag along dir on body_level, 1: final kinetic energy */
+  int body_level;
+  double dir[3];
+  double nsub; /* number of body-level collisions in the run */
+} oadj_obj;
+
+/* reverse of collide_level with input snapshot g; adds the drag seed first */
+static void adj_collide(ora_t *o, int l, int skip_outer, const double *g, const oadj_obj *ob) {
+  olevel *L = &o->lev[l];
+  int Q = o->Q;
+  for (int64_t n = 0; n < L->nn; ++n) {
+    if (L->solid[n]) continue;
+    if (skip_outer && L->pd[n] == 0) continue;
+    double *lo = &L->lf[(size_t)n * Q];
+    if (ob->objective == 0 && l == ob->body_level) {
+      for (int i = 0; i < Q; ++i) {
+        int64_t y[3];
+        for (int a = 0; a < 3; ++a) y[a] = L->pos[3 * n + a] + o->c[i][a];
+        if (!canon(o, l, y)) continue;
+        int64_t m = node_id(o, l, y);
+        if (m >= 0 && L->solid[m]) {
+          double cd = 0;
+          for (int a = 0; a < 3; ++a) cd += o->c[i][a] * ob->dir[a];
+          lo[i] += 2.0 * cd / ob->nsub;
+        }
+      }
+    }
+    double F[3], lFn[3] = {0, 0, 0}, lin[OMAXQ];
+    node_force(o, l, n, F);
+    ora_kbc_adj(o->D, L->beta, &g[(size_t)n * Q], F, lo, lin, lFn);
+    for (int i = 0; i < Q; ++i) {
+      L->lg[(size_t)n * Q + i] += lin[i];
+      lo[i] = 0.0;
+    }
+    /* the node force is (uniform + field) / 2^l */
+    double s = 1.0 / (double)(1 << l);
+    for (int a = 0; a < 3; ++a) L->lF[3 * n + a] += lFn[a] * s;
+  }
+}
+
+/* composite point value source: 1 = child node, 0 = parent node */
+static int point_src(const ora_t *o, int lp, const int64_t Xin[3], int64_t *node) {
+  int64_t X[3] = {Xin[0], Xin[1], Xin[2]};
+  canon(o, lp, X);
+  int64_t xc[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+  if (canon(o, lp + 1, xc) && in_region(o, lp + 1, xc) && dist_at(o, lp + 1, xc) >= 2) {
+    *node = node_id(o, lp + 1, xc);
+    return 1;
+  }
+  *node = node_id(o, lp, X);
+  return 0;
+}
+
+/* reverse of couple with snapshots gp (parent) and gc (child) of the inputs */
+static void adj_couple(ora_t *o, int lp, const double *gp, const double *gc) {
+  olevel *P = &o->lev[lp], *C = &o->lev[lp + 1];
+  int Q = o->Q, D = o->D;
+  static const double w4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
+  double fac_pc = P->beta / (2.0 * C->beta), fac_cp = 2.0 * C->beta / P->beta;
+  /* adjoints of the written values, then clear them */
+  double *lwc = (double *)calloc((size_t)(C->nn ? C->nn : 1) * Q, sizeof(double));
+  double *lwp = (double *)calloc((size_t)(P->nn ? P->nn : 1) * Q, sizeof(double));
+  for (int64_t n = 0; n < C->nn; ++n)
+    if (!C->solid[n] && C->pd[n] <= 1)
+      for (int i = 0; i < Q; ++i) {
+        lwc[(size_t)n * Q + i] = C->lg[(size_t)n * Q + i];
+        C->lg[(size_t)n * Q + i] = 0.0;
+      }
+  for (int64_t n = 0; n < P->nn; ++n)
+    if (P->ring[n])
+      for (int i = 0; i < Q; ++i) {
+        lwp[(size_t)n * Q + i] = P->lg[(size_t)n * Q + i];
+        P->lg[(size_t)n * Q + i] = 0.0;
+      }
+  /* fine interface nodes: g = f^eq(rho~, u~) + n~, tensor interpolation of points */
+  for (int64_t n = 0; n < C->nn; ++n) {
+    if (C->solid[n] || C->pd[n] > 1) continue;
+    const int64_t *x = &C->pos[3 * n];
+    int npt[3] = {1, 1, 1};
+    int64_t pts[3][4];
+    double wts[3][4];
+    for (int a = 0; a < 3; ++a) {
+      if (a < D && (x[a] & 1)) {
+        npt[a] = 4;
+        for (int k = 0; k < 4; ++k) {
+          pts[a][k] = (x[a] - 3 + 2 * k) / 2;
+          wts[a][k] = w4[k];
+        }
+      } else {
+        pts[a][0] = x[a] / 2;
+        wts[a][0] = 1.0;
+      }
+    }
+    /* forward values at the node */
+    double rr = 0, uu[3] = {0, 0, 0};
+    for (int kz = 0; kz < npt[2]; ++kz)
+      for (int ky = 0; ky < npt[1]; ++ky)
+        for (int kx = 0; kx < npt[0]; ++kx) {
+          int64_t X[3] = {pts[0][kx], pts[1][ky], pts[2][kz]}, m;
+          double w = wts[0][kx] * wts[1][ky] * wts[2][kz], r, u[3], fn[OMAXQ];
+          int ch = point_src(o, lp, X, &m);
+          node_macro(o, ch ? &gc[(size_t)m * Q] : &gp[(size_t)m * Q], &r, u, fn);
+          rr += w * r;
+          for (int a = 0; a < 3; ++a) uu[a] += w * u[a];
+        }
+    const double *lR = &lwc[(size_t)n * Q];
+    double lr = 0, lu[3] = {0, 0, 0};
+    feq_T(D, rr, uu, lR, &lr, lu);
+    for (int kz = 0; kz < npt[2]; ++kz)
+      for (int ky = 0; ky < npt[1]; ++ky)
+        for (int kx = 0; kx < npt[0]; ++kx) {
+          int64_t X[3] = {pts[0][kx], pts[1][ky], pts[2][kz]}, m;
+          double w = wts[0][kx] * wts[1][ky] * wts[2][kz];
+          int ch = point_src(o, lp, X, &m);
+          double lrw = w * lr, luw[3] = {w * lu[0], w * lu[1], w * lu[2]}, lnw[OMAXQ];
+          for (int i = 0; i < Q; ++i) lnw[i] = w * lR[i];
+          if (ch) macro_T(o, &gc[(size_t)m * Q], 1.0, lrw, luw, lnw, &C->lg[(size_t)m * Q]);
+          else macro_T(o, &gp[(size_t)m * Q], fac_pc, lrw, luw, lnw, &P->lg[(size_t)m * Q]);
+        }
+  }
+  /* parent ring: g = f^eq + fac_cp (g_c - f^eq) with (rho, u) of the fine twin g_c */
+  for (int64_t n = 0; n < P->nn; ++n) {
+    if (!P->ring[n]) continue;
+    int64_t xc[3] = {2 * P->pos[3 * n], 2 * P->pos[3 * n + 1], 2 * P->pos[3 * n + 2]};
+    int64_t m = node_id(o, lp + 1, xc);
+    const double *lw = &lwp[(size_t)n * Q];
+    double lnn[OMAXQ], r = 0, u[3] = {0, 0, 0}, fn[OMAXQ], lr = 0, lu[3] = {0, 0, 0}, lfe[OMAXQ];
+    /* value = feq + fac (g - feq) = fac g + (1 - fac) feq(rho(g), u(g)) */
+    node_macro(o, &gc[(size_t)m * Q], &r, u, fn);
+    for (int i = 0; i < Q; ++i) {
+      C->lg[(size_t)m * Q + i] += fac_cp * lw[i];
+      lfe[i] = (1.0 - fac_cp) * lw[i];
+      lnn[i] = 0.0;
+    }
+    feq_T(D, r, u, lfe, &lr, lu);
+    macro_T(o, &gc[(size_t)m * Q], 0.0, lr, lu, lnn, &C->lg[(size_t)m * Q]);
+  }
+  free(lwc);
+  free(lwp);
+}
+
+/* Run n coarse steps forward from the current state, evaluating the objective, then
+ * the reverse sweep.  Afterwards the state is the final forward state; the adjoint of
+ * the initial state and the force-field gradient are available from
+ * ora_adjoint_state / ora_adjoint_force. */
+int ora_adjoint_run(ora_t *o, int n, int objective, int body_level, const double dir[3], double *J_out) {
+  if (!o->finalized) return fail(o, -2, "adjoint before finalize");
+  if (objective == 0 && (body_level < 0 || body_level >= o->L)) return fail(o, -1, "bad body level");
+  int Q = o->Q;
+  /* states s_0 .. s_n */
+  double **states = (double **)calloc((size_t)(n + 1) * o->L, sizeof(double *));
+  for (int l = 0; l < o->L; ++l) {
+    olevel *L = &o->lev[l];
+    free(L->lf);
+    free(L->lg);
+    free(L->lF);
+    L->lf = (double *)calloc((size_t)(L->nn ? L->nn : 1) * Q, sizeof(double));
+    L->lg = (double *)calloc((size_t)(L->nn ? L->nn : 1) * Q, sizeof(double));
+    L->lF = (double *)calloc((size_t)(L->nn ? L->nn : 1) * 3, sizeof(double));
+    states[l] = dup_arr(L->f, (size_t)L->nn * Q);
+  }
+  oadj_obj ob;
+  ob.objective = objective;
+  ob.body_level = body_level;
+  for (int a = 0; a < 3; ++a) ob.dir[a] = dir ? dir[a] : 0.0;
+  ob.nsub = objective == 0 ? (double)n * (double)(1 << body_level) : 1.0;
+  int rc = 0;
+  double J = 0;
+  if (objective == 0) ora_drag(o, body_level, (double[3]){0, 0, 0}, NULL, 1);
+  for (int k = 1; k <= n && !rc; ++k) {
+    rc = ora_advance(o, 1);
+    for (int l = 0; l < o->L; ++l) states[(size_t)k * o->L + l] = dup_arr(o->lev[l].f, (size_t)o->lev[l].nn * Q);
+  }
+  if (rc) goto done;
+  if (objective == 0) {
+    double F[3];
+    int64_t st;
+    ora_drag(o, body_level, F, &st, 1);
+    J = (F[0] * ob.dir[0] + F[1] * ob.dir[1] + F[2] * ob.dir[2]) / ob.nsub;
+  } else {
+    /* J = 1/2 sum_l sum_x w rho |u|^2 with rho u = j - F/2 at the final state */
+    for (int l = 0; l < o->L; ++l) {
+      olevel *L = &o->lev[l];
+      for (int64_t m = 0; m < L->nn; ++m) {
+        if (L->w[m] == 0.0) continue;
+        double r = 0, j[3] = {0, 0, 0}, F[3];
+        for (int i = 0; i < Q; ++i) {
+          r += L->f[(size_t)m * Q + i];
+          for (int a = 0; a < 3; ++a) j[a] += o->c[i][a] * L->f[(size_t)m * Q + i];
+        }
+        node_force(o, l, m, F);
+        double p[3] = {j[0] - 0.5 * F[0], j[1] - 0.5 * F[1], j[2] - 0.5 * F[2]};
+        double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        J += 0.5 * L->w[m] * p2 / r;
+        for (int i = 0; i < Q; ++i) {
+          double pc = p[0] * o->c[i][0] + p[1] * o->c[i][1] + p[2] * o->c[i][2];
+          L->lf[(size_t)m * Q + i] += L->w[m] * (pc / r - 0.5 * p2 / (r * r));
+        }
+        double s = 1.0 / (double)(1 << l);
+        for (int a = 0; a < 3; ++a) L->lF[3 * m + a] += -0.5 * L->w[m] * p[a] / r * s;
+      }
+    }
+  }
+  /* reverse sweep over coarse steps */
+  for (int k = n; k >= 1 && !rc; --k) {
+    for (int l = 0; l < o->L; ++l)
+      memcpy(o->lev[l].f, states[(size_t)(k - 1) * o->L + l], sizeof(double) * (size_t)o->lev[l].nn * Q);
+    o->taping = 1;
+    tape_clear(o);
+    rc = ora_advance(o, 1);
+    o->taping = 0;
+    if (rc) break;
+    for (int t = o->ntape - 1; t >= 0; --t) {
+      otape *tp = &o->tape[t];
+      if (tp->op == 0) adj_stream(o, tp->level);
+      else if (tp->op == 1) adj_collide(o, tp->level, tp->skip, tp->g0, &ob);
+      else adj_couple(o, tp->level, tp->g0, tp->g1);
+    }
+    tape_clear(o);
+  }
+  /* leave the final forward state */
+  for (int l = 0; l < o->L; ++l)
+    memcpy(o->lev[l].f, states[(size_t)n * o->L + l], sizeof(double) * (size_t)o->lev[l].nn * Q);
+  if (objective == 0) ora_drag(o, body_level, (double[3]){0, 0, 0}, NULL, 1);
+done:
+  for (size_t k = 0; k < (size_t)(n + 1) * o->L; ++k) free(states[k]);
+  free(states);
+  if (J_out) *J_out = J;
+  return rc;
+}
+
+/* adjoint of the initial post-collision state, dense [Q][box] */
+int ora_adjoint_state(const ora_t *o, int l, double *out) {
+  if (!o->finalized || l < 0 || l >= o->L || !o->lev[l].lf) return -1;
+  const olevel *L = &o->lev[l];
+  int64_t tot = L->bn[0] * L->bn[1] * L->bn[2];
+  for (int64_t k = 0; k < tot; ++k) {
+    int32_t n = L->id[k];
+    for (int i = 0; i < o->Q; ++i) out[i * tot + k] = (n < 0 || L->solid[n]) ? 0.0 : L->lf[(size_t)n * o->Q + i];
+  }
+  return 0;
+}
+
+/* gradient with respect to the per-node force-density field of a level (level-0
+ * units), dense [D][box] */
+int ora_adjoint_force(const ora_t *o, int l, double *out) {
+  if (!o->finalized || l < 0 || l >= o->L || !o->lev[l].lF) return -1;
+  const olevel *L = &o->lev[l];
+  int64_t tot = L->bn[0] * L->bn[1] * L->bn[2];
+  for (int64_t k = 0; k < tot; ++k) {
+    int32_t n = L->id[k];
+    for (int a = 0; a < o->D; ++a) out[a * tot + k] = (n < 0 || L->solid[n]) ? 0.0 : L->lF[3 * n + a];
+  }
+  return 0;
+}
+
+/* gradient with respect to the initial velocity field, through
+ * f_i = f^eq_i(rho0, u0)(1 + noise_i); lam = adjoint of the initial state [Q][box] */
+int ora_init_adjoint_u(int D, int64_t tot, const double *rho, const double *u, const double *noise,
+                       const double *lam, double *out) {
+  int Q = D == 2 ? 9 : 27;
+  for (int64_t k = 0; k < tot; ++k) {
+    double uu[3] = {0, 0, 0}, lr = 0, lu[3] = {0, 0, 0}, lf[OMAXQ];
+    for (int a = 0; a < D; ++a) uu[a] = u[a * tot + k];
+    for (int i = 0; i < Q; ++i) lf[i] = lam[i * tot + k] * (noise ? 1.0 + noise[i * tot + k] : 1.0);
+    feq_T(D, rho[k], uu, lf, &lr, lu);
+    for (int a = 0; a < D; ++a) out[a * tot + k] = lu[a];
   }
   return 0;
 }

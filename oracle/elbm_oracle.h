@@ -59,6 +59,16 @@ double ora_kbc(int D, double beta, const double *f, const double F[3], double *o
                double *dh);
 double ora_beta(double nu);
 
+/* discrete adjoint (reverse mode of the coarse step above) */
+void ora_kbc_adj(int D, double beta, const double *f, const double F[3], const double *lo, double *lf,
+                 double lF[3]);
+int ora_adjoint_run(ora_t *o, int n_coarse_steps, int objective, int body_level, const double dir[3],
+                    double *J_out);
+int ora_adjoint_state(const ora_t *o, int level, double *out);
+int ora_adjoint_force(const ora_t *o, int level, double *out);
+int ora_init_adjoint_u(int D, int64_t n, const double *rho, const double *u, const double *noise,
+                       const double *lam, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -159,7 +159,8 @@ def channel3d(nx: int = 128, ny: int = 64, nz: int = 64, slab: int = 8, nu0: flo
 
 
 def sphere3d(nx: int = 256, ny: int = 128, nz: int = 128, U: float = 0.05, Re: float = 300.0, D_fine: float = 20.0,
-             l1=((48, 48, 48), (112, 80, 80)), l2=((56, 56, 56), (88, 72, 72)), centre=(64, 64, 64)) -> Spec:
+             l1=((48, 48, 48), (112, 80, 80)), l2=((56, 56, 56), (88, 72, 72)), centre=(64, 64, 64),
+             noise: float = 0.0, seed: int = SEED) -> Spec:
     """Sphere of diameter D_fine (finest-level units) at `centre` (coarse coords);
     three levels with boxes l1, l2 in coarse coordinates; inlet at x=0, outflow at
     x=nx-1, periodic in y and z."""
@@ -170,7 +171,8 @@ def sphere3d(nx: int = 256, ny: int = 128, nz: int = 128, U: float = 0.05, Re: f
         shp = tuple(int(v) for v in n[:3][::-1])
         u = np.zeros((3,) + shp)
         u[0] = U
-        return np.ones(shp), u, None
+        nzs = noise * rng(seed + 13 * level).uniform(-1.0, 1.0, size=(27,) + shp) if noise else None
+        return np.ones(shp), u, nzs
 
     def sc(b, s):
         return tuple(int(v) * s for v in b)
