@@ -103,6 +103,7 @@ def run_gpu(sp, storage, steps, warmup, tune):
         lat.init(l, rho, u, nz)
     if tune:
         lat.tune(os.environ.get("ELBM_TUNE_CACHE"), steps=3)
+    print("bench: %s launch %s" % (storage, lat.get_launch()), file=sys.stderr, flush=True)
     lat.advance(warmup)
     lat.synchronize()
     torch.cuda.synchronize()
@@ -194,7 +195,7 @@ def main():
         "config": {"workload": desc, "levels": sp.levels,
                    "fluid_nodes_per_level": [lat.level_info(l)[1] for l in range(sp.levels)],
                    "fine_equiv_updates_per_step": fe, "storage": args.storage, "compute": "f32" if
-                   args.storage != "f64" else "f64", "graph": True},
+                   args.storage != "f64" else "f64", "launch": lat.get_launch()},
         "hbm_pct_alg": round(hbm_pct, 2),
         "stable": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -171,6 +171,8 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
  * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD). */
 elbm_status elbm_set_launch(elbm_ctx *ctx, int use_graph, int wg_per_cu, int xcd_remap, int threads,
                             int occupancy);
+/* Current launch configuration: {use_graph, wg_per_cu, xcd_remap, threads, occupancy}. */
+elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[5]);
 /* Autotune the launch configuration by timing `steps` coarse steps per candidate;
  * results cached in cache_path (one "key": [graph, wg_per_cu, xcd, threads, occupancy]
  * line per workload shape; may be NULL).  The state is restored; drag accumulators

@@ -72,13 +72,18 @@ struct Level {
 
 struct Pair {
   std::vector<GPoint> pts;
-  std::vector<CItem> items;
+  std::vector<CItem> items;  // fine interface items (kind 0), stencils in global slots
+  std::vector<CItem> ring;   // coarse ring items (kind 1)
+  std::vector<CTile> tiles;  // item0 / pt0 relative to this pair's arrays
+  std::vector<int32_t> tile_rows;
+  std::vector<CItem> titems;  // fine items in tile order, stencils in tile rows
+  std::vector<StencilEntry> tsten;
   double fac_pc = 1, fac_cp = 1;
 };
 
 struct Tick {
   int lmin;
-  size_t sc_off, sc_n, gp_off, gp_n, ci_off, ci_n;
+  size_t sc_off, sc_n, gp_off, gp_n, tile_off, tile_n, ring_off, ring_n;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -98,14 +103,17 @@ struct elbm_ctx {
   std::vector<Tick> ticks;
   std::vector<WorkItem> sc_all, red_items;
   std::vector<GPoint> gp_all;
-  std::vector<CItem> ci_all;
-  std::vector<StencilEntry> sten;
+  std::vector<CItem> fine_all, ring_all;
+  std::vector<CTile> tiles_all;
+  std::vector<int32_t> tile_rows_all;
+  std::vector<StencilEntry> sten, tsten_all;
+  int lds_rows = 1;
   int stage_cols = 0;
   bool finalized = false, bound = false;
   std::string err;
   // workspace layout
-  size_t ws_need = 0, o_levstatic = 0, o_pairstatic = 0, o_sc = 0, o_gp = 0, o_ci = 0, o_sten = 0, o_stage = 0,
-         o_redit = 0, o_part = 0, o_res = 0, o_tmp = 0;
+  size_t ws_need = 0, o_levstatic = 0, o_pairstatic = 0, o_sc = 0, o_gp = 0, o_fine = 0, o_ring = 0, o_tiles = 0,
+         o_trows = 0, o_sten = 0, o_stage = 0, o_redit = 0, o_part = 0, o_res = 0, o_tmp = 0;
   size_t tmp_bytes = 0;
   char *ws = nullptr;
   hipStream_t stream = nullptr, side = nullptr, cap = nullptr;
@@ -736,8 +744,53 @@ elbm_status build_pairs(elbm_ctx *c) {
             }
         P.items.push_back(it);
       }
-    // uniform stencil sizes within a wavefront: longest stencils first
-    std::stable_sort(P.items.begin(), P.items.end(), [](const CItem &x, const CItem &y) { return x.b > y.b; });
+    // tiles: fine interface nodes of one brick, longest stencils first (uniform loop
+    // counts within a wavefront), split when the distinct rows exceed the LDS budget
+    {
+      const int maxr = couple_max_rows(D, c->storage);
+      std::vector<CItem> its = P.items;
+      std::stable_sort(its.begin(), its.end(), [](const CItem &x, const CItem &y) {
+        return x.brick != y.brick ? x.brick < y.brick : x.b > y.b;
+      });
+      size_t k = 0;
+      while (k < its.size()) {
+        const int32_t br = its[k].brick;
+        CTile t;
+        t.item0 = (int32_t)P.titems.size();
+        t.pt0 = (int32_t)P.tile_rows.size();
+        t.nitem = 0;
+        t.npt = 0;
+        std::unordered_map<int32_t, int32_t> local;
+        while (k < its.size() && its[k].brick == br) {
+          const CItem &it = its[k];
+          int add = 0;
+          for (int e = it.a; e < it.a + it.b; ++e) add += local.count(c->sten[e].slot) ? 0 : 1;
+          if (t.npt + add > maxr && t.nitem > 0) break;  // close the tile, same brick continues
+          CItem ti = it;
+          ti.a = (int32_t)P.tsten.size();
+          for (int e = it.a; e < it.a + it.b; ++e) {
+            auto f = local.find(c->sten[e].slot);
+            int32_t li;
+            if (f == local.end()) {
+              li = t.npt++;
+              local[c->sten[e].slot] = li;
+              P.tile_rows.push_back(c->sten[e].slot);
+            } else {
+              li = f->second;
+            }
+            StencilEntry se;
+            se.slot = li;
+            se.w = c->sten[e].w;
+            P.tsten.push_back(se);
+          }
+          P.titems.push_back(ti);
+          t.nitem++;
+          ++k;
+        }
+        c->lds_rows = std::max(c->lds_rows, (int)t.npt);
+        P.tiles.push_back(t);
+      }
+    }
     // parent ring
     for (int32_t b = 0; b < Lp.nb; ++b)
       for (int n = 0; n < BN; ++n) {
@@ -760,7 +813,7 @@ elbm_status build_pairs(elbm_ctx *c) {
         it.kind = 1;
         it.a = r.brick;
         it.b = r.node;
-        P.items.push_back(it);
+        P.ring.push_back(it);
       }
   }
   c->stage_cols = slots;
@@ -771,18 +824,38 @@ void build_schedule(elbm_ctx *c) {
   c->ticks.clear();
   c->sc_all.clear();
   c->gp_all.clear();
-  c->ci_all.clear();
+  c->fine_all.clear();
+  c->ring_all.clear();
+  c->tiles_all.clear();
+  c->tile_rows_all.clear();
+  c->tsten_all.clear();
   // pair lists laid out by parent level so that the pairs of a tick are contiguous
-  std::vector<size_t> gp_start(c->L + 1, 0), ci_start(c->L + 1, 0);
+  std::vector<size_t> gp_start(c->L + 1, 0), tl_start(c->L + 1, 0), rg_start(c->L + 1, 0);
   for (int p = 0; p + 1 < c->L; ++p) {
+    const Pair &P = c->pairs[p];
     gp_start[p] = c->gp_all.size();
-    ci_start[p] = c->ci_all.size();
-    c->gp_all.insert(c->gp_all.end(), c->pairs[p].pts.begin(), c->pairs[p].pts.end());
-    c->ci_all.insert(c->ci_all.end(), c->pairs[p].items.begin(), c->pairs[p].items.end());
+    tl_start[p] = c->tiles_all.size();
+    rg_start[p] = c->ring_all.size();
+    c->gp_all.insert(c->gp_all.end(), P.pts.begin(), P.pts.end());
+    const int32_t item_base = (int32_t)c->fine_all.size(), row_base = (int32_t)c->tile_rows_all.size();
+    const int32_t sten_base = (int32_t)c->tsten_all.size();
+    for (CTile t : P.tiles) {
+      t.item0 += item_base;
+      t.pt0 += row_base;
+      c->tiles_all.push_back(t);
+    }
+    for (CItem it : P.titems) {
+      it.a += sten_base;
+      c->fine_all.push_back(it);
+    }
+    c->tile_rows_all.insert(c->tile_rows_all.end(), P.tile_rows.begin(), P.tile_rows.end());
+    c->tsten_all.insert(c->tsten_all.end(), P.tsten.begin(), P.tsten.end());
+    c->ring_all.insert(c->ring_all.end(), P.ring.begin(), P.ring.end());
   }
   const int pL = c->L > 1 ? c->L - 1 : 0;
   gp_start[pL] = c->gp_all.size();
-  ci_start[pL] = c->ci_all.size();
+  tl_start[pL] = c->tiles_all.size();
+  rg_start[pL] = c->ring_all.size();
   const int T = 1 << (c->L - 1);
   for (int t = 1; t <= T; ++t) {
     int lmin = c->L - 1;
@@ -799,10 +872,13 @@ void build_schedule(elbm_ctx *c) {
       c->sc_all.insert(c->sc_all.end(), v.begin(), v.end());
     }
     tk.sc_n = c->sc_all.size() - tk.sc_off;
-    tk.gp_off = gp_start[std::min(lmin, pL)];
+    const int p0 = std::min(lmin, pL);
+    tk.gp_off = gp_start[p0];
     tk.gp_n = gp_start[pL] - tk.gp_off;
-    tk.ci_off = ci_start[std::min(lmin, pL)];
-    tk.ci_n = ci_start[pL] - tk.ci_off;
+    tk.tile_off = tl_start[p0];
+    tk.tile_n = tl_start[pL] - tk.tile_off;
+    tk.ring_off = rg_start[p0];
+    tk.ring_n = rg_start[pL] - tk.ring_off;
     c->ticks.push_back(tk);
   }
   c->red_items.clear();
@@ -847,8 +923,11 @@ void build_layout(elbm_ctx *c) {
   c->o_pairstatic = take(sizeof(PairStatic) * MAXL);
   c->o_sc = take(c->sc_all.size() * sizeof(WorkItem));
   c->o_gp = take(c->gp_all.size() * sizeof(GPoint));
-  c->o_ci = take(c->ci_all.size() * sizeof(CItem));
-  c->o_sten = take(c->sten.size() * sizeof(StencilEntry));
+  c->o_fine = take(c->fine_all.size() * sizeof(CItem));
+  c->o_ring = take(c->ring_all.size() * sizeof(CItem));
+  c->o_tiles = take(c->tiles_all.size() * sizeof(CTile));
+  c->o_trows = take(c->tile_rows_all.size() * sizeof(int32_t));
+  c->o_sten = take(c->tsten_all.size() * sizeof(StencilEntry));
   c->o_stage = take((size_t)stage_row_width(c->D) * std::max(c->stage_cols, 1) * comp_bytes(c->storage));
   c->o_redit = take(c->red_items.size() * sizeof(WorkItem));
   c->o_part = take(c->red_items.size() * 5 * 8);
@@ -924,14 +1003,13 @@ elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_
   }
   const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
   const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
-  const bool coupling = tk.ci_n > 0;
+  const bool coupling = tk.tile_n + tk.ring_n > 0;
   hipStream_t cs = main;
   if (coupling && fork) {
-    hipEvent_t ef = c->ev_fork[(t - 1) % 64], ej = c->ev_join[(t - 1) % 64];
+    hipEvent_t ef = c->ev_fork[(t - 1) % 64];
     HIPCK(c, hipEventRecord(ef, main));
     HIPCK(c, hipStreamWaitEvent(side, ef, 0));
     cs = side;
-    (void)ej;
   }
   if (coupling) {
     GatherArgs g;
@@ -944,8 +1022,13 @@ elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_
     for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
     LCK(c, launch_gather(c->D, c->storage, g, cs));
     CoupleArgs a;
-    a.items = (const CItem *)(c->ws + c->o_ci) + tk.ci_off;
-    a.n = (int)tk.ci_n;
+    a.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
+    a.n_tiles = (int)tk.tile_n;
+    a.lds_rows = c->lds_rows;
+    a.tile_rows = (const int32_t *)(c->ws + c->o_trows);
+    a.items = (const CItem *)(c->ws + c->o_fine);
+    a.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;
+    a.n_ring = (int)tk.ring_n;
     a.stride = stage_row_width(c->D);
     a.sten = (const StencilEntry *)(c->ws + c->o_sten);
     a.stage = c->ws + c->o_stage;
@@ -1302,10 +1385,20 @@ elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
     HIPCK(c, hipMemcpy(c->ws + c->o_sc, c->sc_all.data(), c->sc_all.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   if (!c->gp_all.empty())
     HIPCK(c, hipMemcpy(c->ws + c->o_gp, c->gp_all.data(), c->gp_all.size() * sizeof(GPoint), hipMemcpyHostToDevice));
-  if (!c->ci_all.empty())
-    HIPCK(c, hipMemcpy(c->ws + c->o_ci, c->ci_all.data(), c->ci_all.size() * sizeof(CItem), hipMemcpyHostToDevice));
-  if (!c->sten.empty())
-    HIPCK(c, hipMemcpy(c->ws + c->o_sten, c->sten.data(), c->sten.size() * sizeof(StencilEntry),
+  if (!c->fine_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_fine, c->fine_all.data(), c->fine_all.size() * sizeof(CItem),
+                       hipMemcpyHostToDevice));
+  if (!c->ring_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_ring, c->ring_all.data(), c->ring_all.size() * sizeof(CItem),
+                       hipMemcpyHostToDevice));
+  if (!c->tiles_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_tiles, c->tiles_all.data(), c->tiles_all.size() * sizeof(CTile),
+                       hipMemcpyHostToDevice));
+  if (!c->tile_rows_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_trows, c->tile_rows_all.data(), c->tile_rows_all.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+  if (!c->tsten_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_sten, c->tsten_all.data(), c->tsten_all.size() * sizeof(StencilEntry),
                        hipMemcpyHostToDevice));
   if (!c->red_items.empty())
     HIPCK(c, hipMemcpy(c->ws + c->o_redit, c->red_items.data(), c->red_items.size() * sizeof(WorkItem),
@@ -1534,6 +1627,16 @@ elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_r
   c->threads = threads;
   c->occ = occupancy;
   invalidate_graphs(c);
+  return ELBM_OK;
+}
+
+elbm_status elbm_get_launch(const elbm_ctx *c, int32_t cfg[5]) {
+  if (!c || !cfg) return ELBM_EINVAL;
+  cfg[0] = c->use_graph;
+  cfg[1] = c->wg_per_cu;
+  cfg[2] = c->xcd_remap;
+  cfg[3] = c->threads;
+  cfg[4] = c->occ;
   return ELBM_OK;
 }
 

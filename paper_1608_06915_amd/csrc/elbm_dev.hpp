@@ -59,8 +59,13 @@ struct CItem {  // node rebuilt by the coupling phase
 };
 
 struct StencilEntry {
-  int32_t slot;
+  int32_t slot;  // staged row (untiled) or row in the tile's LDS copy (tiled)
   float w;
+};
+
+struct CTile {  // fine interface nodes of one brick whose stencils share staged rows
+  int32_t item0, nitem;  // fine interface items
+  int32_t pt0, npt;      // staged rows copied to LDS
 };
 
 struct LevelStatic {  // device-resident per-level constants and table pointers
@@ -106,8 +111,13 @@ struct GatherArgs {
 };
 
 struct CoupleArgs {
-  const CItem *items;
-  int32_t n;
+  const CTile *tiles;     // fine interface tiles of the tick
+  int32_t n_tiles;
+  int32_t lds_rows;       // rows of the dynamic LDS buffer
+  const int32_t *tile_rows;  // staged row index per tile row
+  const CItem *items;     // fine interface items (kind 0) referenced by the tiles
+  const CItem *ring;      // coarse ring items (kind 1) of the tick
+  int32_t n_ring;
   int32_t stride;
   const StencilEntry *sten;
   const void *stage;
@@ -141,6 +151,7 @@ int launch_reduce(int D, int st, void *const *pops, const LevelStatic *lev_dev, 
 int launch_force_scatter(int D, float *force, const double *F, int nbricks, const int32_t *borg, Dims box,
                          void *stream);
 int stage_row_width(int D);
+int couple_max_rows(int D, int st);
 int launch_zero(void *p, size_t bytes, void *stream);
 int launch_copy(void *dst, const void *src, size_t bytes, void *stream);
 

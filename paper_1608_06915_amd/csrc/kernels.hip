@@ -11,352 +11,9 @@
 // and f_i^eq - W_i = W_i q_i with q_i = (1 + drho) prod_a (1 + a_a) - 1 accumulated as
 // q <- q + a + q a.  The inverse equilibrium for the entropic scalar product is the
 // product of per-axis reciprocals (3 per axis instead of one per population).
-#include <hip/hip_fp16.h>
-#include <hip/hip_runtime.h>
-
-#include "elbm_dev.hpp"
+#include "lbm_device.hpp"
 
 namespace elbm {
-
-// ---------------------------------------------------------------- lattice constants
-__host__ __device__ constexpr int cxo(int i) { return i % 3 - 1; }
-__host__ __device__ constexpr int cyo(int i) { return (i / 3) % 3 - 1; }
-template <int D> __host__ __device__ constexpr int czo(int i) { return D == 3 ? i / 9 - 1 : 0; }
-template <int D> __host__ __device__ constexpr int nq() { return D == 2 ? 9 : 27; }
-__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
-template <int D> __host__ __device__ constexpr double wgt(int i) {
-  return w1(cxo(i)) * w1(cyo(i)) * (D == 3 ? w1(czo<D>(i)) : 1.0);
-}
-
-// ---------------------------------------------------------------- storage codecs
-template <int ST> struct Codec;
-template <> struct Codec<ST_F64> {
-  typedef double S;
-  typedef double T;
-  __device__ static inline T ld(const S *p, T w) { return *p - w; }
-  __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
-};
-template <> struct Codec<ST_F32> {
-  typedef float S;
-  typedef float T;
-  __device__ static inline T ld(const S *p, T w) { return *p - w; }
-  __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
-};
-template <> struct Codec<ST_F16S> {
-  typedef uint16_t S;
-  typedef float T;
-  __device__ static inline T ld(const S *p, T) { return __half2float(__ushort_as_half(*p)); }
-  __device__ static inline void st(S *p, T h, T) { *p = __half_as_ushort(__float2half_rn(h)); }
-};
-template <> struct Codec<ST_BF16S> {
-  typedef uint16_t S;
-  typedef float T;
-  __device__ static inline T ld(const S *p, T) { return __uint_as_float(((uint32_t)*p) << 16); }
-  __device__ static inline void st(S *p, T h, T) {
-    uint32_t b = __float_as_uint(h);
-    if ((b & 0x7fffffffu) > 0x7f800000u) {
-      *p = (uint16_t)0x7fc0u;
-    } else {
-      b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
-      *p = (uint16_t)(b >> 16);
-    }
-  }
-};
-
-// FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
-// division and square root.
-__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double rcp(double x) { return 1.0 / x; }
-__device__ inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ inline double sqrt_(double x) { return sqrt(x); }
-
-// ---------------------------------------------------------------- equilibrium
-// per-axis a(c) = phi(c) - 1 for c = -1, 0, +1 (index c+1)
-template <typename T> __device__ inline void axis_factors(T u, T a[3]) {
-  T t = T(3) * u * u;
-  T sig = t * rcp(T(1) + sqrt_(T(1) + t));
-  a[0] = T(2) * sig - T(3) * u;
-  a[1] = -sig;
-  a[2] = T(2) * sig + T(3) * u;
-}
-
-// partial products over x and y: qxy[cx+1 + 3(cy+1)] = (1+drho)(1+ax)(1+ay) - 1
-template <typename T> __device__ inline void q_table(T drho, const T (&a)[3][3], T (&qxy)[9]) {
-#pragma unroll
-  for (int cx = 0; cx < 3; ++cx) {
-    const T qx = fma(drho, a[0][cx], drho + a[0][cx]);
-#pragma unroll
-    for (int cy = 0; cy < 3; ++cy) qxy[cx + 3 * cy] = fma(qx, a[1][cy], qx + a[1][cy]);
-  }
-}
-// q_i = (1 + drho) prod_a phi_a(c_ia) - 1, so that f_i^eq - W_i = W_i q_i
-template <int D, typename T> __device__ inline T q_of(const T (&qxy)[9], const T (&a)[3][3], int i) {
-  T v = qxy[(cxo(i) + 1) + 3 * (cyo(i) + 1)];
-  if (D == 3) {
-    const T b = a[2][czo<D>(i) + 1];
-    v = fma(v, b, v + b);
-  }
-  return v;
-}
-
-template <int D, typename T> __device__ inline void eq_dev(T drho, const T u[3], T (&q)[nq<D>()]) {
-  T a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  axis_factors(u[0], a[0]);
-  axis_factors(u[1], a[1]);
-  if (D == 3) axis_factors(u[2], a[2]);
-  T qxy[9];
-  q_table(drho, a, qxy);
-#pragma unroll
-  for (int i = 0; i < nq<D>(); ++i) q[i] = q_of<D>(qxy, a, i);
-}
-
-template <int D, typename T> __device__ inline void moments(const T (&h)[nq<D>()], T &drho, T (&j)[3]) {
-  drho = 0;
-  j[0] = j[1] = j[2] = 0;
-#pragma unroll
-  for (int i = 0; i < nq<D>(); ++i) {
-    drho += h[i];
-    if (cxo(i) == 1) j[0] += h[i];
-    if (cxo(i) == -1) j[0] -= h[i];
-    if (cyo(i) == 1) j[1] += h[i];
-    if (cyo(i) == -1) j[1] -= h[i];
-    if (D == 3 && czo<D>(i) == 1) j[2] += h[i];
-    if (D == 3 && czo<D>(i) == -1) j[2] -= h[i];
-  }
-}
-
-// ---------------------------------------------------------------- KBC collision
-// Post-collision h' = h - beta (2 ds + gamma dh) (Eq. f_equations with Eq. f_mirr),
-// gamma from Eq. gamma_min_approx, plus the exact-difference forcing of Sec. III.A.
-// h is overwritten by the deviation d = h - (f^eq - W); the post-collision value of
-// population i is handed to st(i, h'_i).  F: force density in level units.
-template <int D, typename T, typename Store>
-__device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_force, Store st) {
-  constexpr int Q = nq<D>();
-  T drho, j[3];
-  moments<D, T>(h, drho, j);
-  const T ir = rcp(T(1) + drho);
-  const T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
-  T a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  axis_factors(u[0], a[0]);
-  axis_factors(u[1], a[1]);
-  if (D == 3) axis_factors(u[2], a[2]);
-  {
-    T qxy[9];
-    q_table(drho, a, qxy);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) h[i] -= T(wgt<D>(i)) * q_of<D>(qxy, a, i);
-  }
-  // deviatoric second moments of d
-  T N1 = 0, N2 = 0, Pxy = 0, Pxz = 0, Pyz = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int x = cxo(i), y = cyo(i), z = czo<D>(i);
-    const T d = h[i];
-    if (D == 2) {
-      const int nn = x * x - y * y;
-      if (nn == 1) N1 += d;
-      if (nn == -1) N1 -= d;
-    } else {
-      const int a1 = x * x - z * z, a2 = y * y - z * z;
-      if (a1 == 1) N1 += d;
-      if (a1 == -1) N1 -= d;
-      if (a2 == 1) N2 += d;
-      if (a2 == -1) N2 -= d;
-      if (x * z == 1) Pxz += d;
-      if (x * z == -1) Pxz -= d;
-      if (y * z == 1) Pyz += d;
-      if (y * z == -1) Pyz -= d;
-    }
-    if (x * y == 1) Pxy += d;
-    if (x * y == -1) Pxy -= d;
-  }
-  // shear-part values (natural-moment basis, trace in h)
-  T sX, sY, sZ = 0;
-  if (D == 2) {
-    sX = T(0.25) * N1;
-    sY = -T(0.25) * N1;
-  } else {
-    const T s6 = T(1.0 / 6.0);
-    sX = (T(2) * N1 - N2) * s6;
-    sY = (T(2) * N2 - N1) * s6;
-    sZ = -(N1 + N2) * s6;
-  }
-  const T pxy = T(0.25) * Pxy, pxz = T(0.25) * Pxz, pyz = T(0.25) * Pyz;
-  auto dsv = [&](int i) -> T {
-    const int x = cxo(i), y = cyo(i), z = czo<D>(i);
-    const int nz = x * x + y * y + z * z;
-    if (nz == 1) return x ? sX : (y ? sY : sZ);
-    if (nz == 2) return (z == 0) ? T(x * y) * pxy : ((y == 0) ? T(x * z) * pxz : T(y * z) * pyz);
-    return T(0);
-  };
-  // entropic scalar products <ds|dh>, <dh|dh> with weight 1/f^eq = (1/(rho W)) prod 1/phi
-  T A = 0, B = 0;
-  {
-    T rxy[9], rz[3] = {1, 1, 1};
-#pragma unroll
-    for (int cx = 0; cx < 3; ++cx) {
-      const T rx = rcp(T(1) + a[0][cx]);
-#pragma unroll
-      for (int cy = 0; cy < 3; ++cy) rxy[cx + 3 * cy] = rx * rcp(T(1) + a[1][cy]);
-    }
-    if (D == 3)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rz[c] = rcp(T(1) + a[2][c]);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T ds = dsv(i);
-      const T dh = h[i] - ds;
-      T ifq = (ir * T(1.0 / wgt<D>(i))) * rxy[(cxo(i) + 1) + 3 * (cyo(i) + 1)];
-      if (D == 3) ifq *= rz[czo<D>(i) + 1];
-      const T dhw = dh * ifq;
-      A = fma(ds, dhw, A);
-      B = fma(dh, dhw, B);
-    }
-  }
-  const T ib = rcp(beta);
-  T gamma = T(2);
-  if (B > T(0)) {
-    const T g = ib - (T(2) - ib) * (A * rcp(B));
-    if (isfinite(g)) gamma = g;
-  }
-  const T b2 = T(2) * beta, bg = beta * gamma;
-  T qxy[9];
-  q_table(drho, a, qxy);
-  if (has_force) {
-    const T u2[3] = {u[0] + F[0] * ir, u[1] + F[1] * ir, D == 3 ? u[2] + F[2] * ir : T(0)};
-    T a2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    axis_factors(u2[0], a2[0]);
-    axis_factors(u2[1], a2[1]);
-    if (D == 3) axis_factors(u2[2], a2[2]);
-    T qxy2[9];
-    q_table(drho, a2, qxy2);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T ds = dsv(i), d = h[i];
-      const T q = q_of<D>(qxy, a, i);
-      const T q2 = q_of<D>(qxy2, a2, i);
-      st(i, T(wgt<D>(i)) * q2 + (d - b2 * ds - bg * (d - ds)));
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T ds = dsv(i), d = h[i];
-      st(i, T(wgt<D>(i)) * q_of<D>(qxy, a, i) + (d - b2 * ds - bg * (d - ds)));
-    }
-  }
-  return gamma;
-}
-
-template <int D, typename T> __device__ inline void node_force(const LevelStatic &L, int brick, int n, T F[3]) {
-  F[0] = T(L.F[0]);
-  F[1] = T(L.F[1]);
-  F[2] = T(L.F[2]);
-  if (L.force) {
-    const float *fp = L.force + (size_t)brick * D * BN + n;
-#pragma unroll
-    for (int a = 0; a < D; ++a) F[a] += T(fp[a * BN]) * T(L.fscale);
-  }
-}
-
-// ---------------------------------------------------------------- pull streaming
-// Sources are addressed as 32-bit byte offsets from the level's population buffer
-// (an SGPR base): offset = brick_offset[neighbour code] + (i*BN + local node)*size.
-template <int B> __device__ inline int side(int s) { return s < 0 ? 0 : (s >= B ? 2 : 1); }
-
-template <int D> struct Lane {
-  // per source displacement k = c+1 along each axis: neighbour code part, local index part
-  int xb[3], xl[3], yzb[9], yzl[9];
-  __device__ inline Lane(int x, int y, int z) {
-    using Bk = Brick<D>;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int sx = x + 1 - k;
-      xb[k] = side<Bk::BX>(sx);
-      xl[k] = sx & (Bk::BX - 1);
-    }
-#pragma unroll
-    for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-      for (int kz = 0; kz < 3; ++kz) {
-        const int sy = y + 1 - ky;
-        const int sz = D == 3 ? z + 1 - kz : 0;
-        yzb[ky + 3 * kz] = 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
-        yzl[ky + 3 * kz] = Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
-      }
-  }
-  __device__ inline int code(int i) const {
-    return xb[cxo(i) + 1] + yzb[(cyo(i) + 1) + 3 * (czo<D>(i) + 1)];
-  }
-  __device__ inline int local(int i) const {
-    return xl[cxo(i) + 1] + yzl[(cyo(i) + 1) + 3 * (czo<D>(i) + 1)];
-  }
-};
-
-template <int D, int ST, typename OFF>
-__device__ inline void pull_plain(const char *__restrict__ srcb, OFF boff, const Lane<D> &ln,
-                                  typename Codec<ST>::T (&h)[nq<D>()]) {
-  using C = Codec<ST>;
-  using S = typename C::S;
-  using T = typename C::T;
-#pragma unroll
-  for (int i = 0; i < nq<D>(); ++i) {
-    const uint32_t off = boff(ln.code(i)) + (uint32_t)((i * BN + ln.local(i)) * (int)sizeof(S));
-    h[i] = C::ld((const S *)(srcb + off), T(wgt<D>(i)));
-  }
-}
-
-template <int D, int ST, typename OFF>
-__device__ inline void pull_special(const char *__restrict__ srcb, OFF boff, const Lane<D> &ln, int n,
-                                    uint8_t cls, uint32_t mask, const LevelStatic &L,
-                                    typename Codec<ST>::T (&h)[nq<D>()]) {
-  using C = Codec<ST>;
-  using S = typename C::S;
-  using T = typename C::T;
-  using Bk = Brick<D>;
-  constexpr int Q = nq<D>();
-  const uint32_t own = boff(13);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const bool hit = (mask >> i) & 1u;
-    if (hit && (cls & CLS_LINKS)) {  // halfway bounce-back: own node, opposite velocity
-      h[i] = C::ld((const S *)(srcb + own + (uint32_t)(((Q - 1 - i) * BN + n) * (int)sizeof(S))),
-                   T(wgt<D>(Q - 1 - i)));
-      continue;
-    }
-    if (hit && (cls & CLS_INLET)) {
-      h[i] = T(L.hin[i]);
-      continue;
-    }
-    if (hit && (cls & CLS_OUTFLOW)) {  // zero gradient: value one node upstream
-      int x = n & (Bk::BX - 1), y = (n >> Bk::LX) & (Bk::BY - 1), z = D == 3 ? n >> (Bk::LX + Bk::LY) : 0;
-      const int sx = x - cxo(i) - L.oshift[0], sy = y - cyo(i) - L.oshift[1], sz = z - czo<D>(i) - L.oshift[2];
-      const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
-      const int loc =
-          (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
-      h[i] = C::ld((const S *)(srcb + boff(code) + (uint32_t)((i * BN + loc) * (int)sizeof(S))), T(wgt<D>(i)));
-      continue;
-    }
-    const uint32_t off = boff(ln.code(i)) + (uint32_t)((i * BN + ln.local(i)) * (int)sizeof(S));
-    h[i] = C::ld((const S *)(srcb + off), T(wgt<D>(i)));
-  }
-}
-
-template <int D> __device__ inline void node_xyz(int n, int &x, int &y, int &z) {
-  using Bk = Brick<D>;
-  x = n & (Bk::BX - 1);
-  y = (n >> Bk::LX) & (Bk::BY - 1);
-  z = D == 3 ? (n >> (Bk::LX + Bk::LY)) : 0;
-}
-
-__device__ inline int xcd_perm(int b, int G) {
-  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range
-  return (b & 7) * (G >> 3) + (b >> 3);
-}
-
-template <int D, int ST> __device__ constexpr uint32_t brick_bytes() {
-  return (uint32_t)(nq<D>() * BN * sizeof(typename Codec<ST>::S));
-}
 
 // ---------------------------------------------------------------- stream-collide
 // OCC: minimum waves per SIMD requested from the register allocator (1: no cap,
@@ -367,59 +24,71 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   using S = typename C::S;
   using T = typename C::T;
   constexpr int Q = nq<D>();
-  __shared__ uint32_t s_off[27];
   __shared__ double s_red[3][8];
   const int G = gridDim.x;
   const int me = (a.remap && (G & 7) == 0) ? xcd_perm(blockIdx.x, G) : blockIdx.x;
   for (int base = 0; base < a.n_items; base += G) {
     const int idx = base + me;
     if (idx >= a.n_items) break;
-    const WorkItem w = a.items[idx];
-    const LevelStatic &L = a.lev[w.level];
-    __syncthreads();
-    if (threadIdx.x < 27) {
-      const int nb = L.nbr[(size_t)w.brick * 27 + threadIdx.x];
-      s_off[threadIdx.x] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-    }
-    __syncthreads();
-    const char *__restrict__ srcb = (const char *)a.src[w.level];
-    S *__restrict__ dst = (S *)a.dst[w.level] + (size_t)w.brick * Q * BN;
+    WorkItem w = a.items[idx];
+    // the item is the same for the whole workgroup: keep it in scalar registers
+    w.brick = __builtin_amdgcn_readfirstlane(w.brick);
+    const int wl = __builtin_amdgcn_readfirstlane((int)w.level);
+    const int wthr = __builtin_amdgcn_readfirstlane((int)w.thr);
+    const int wdrag = __builtin_amdgcn_readfirstlane((int)w.drag);
+    const LevelStatic &L = a.lev[wl];
+    const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
+    uint32_t off[27];
+    static_for<0, 27>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const int nb = __builtin_amdgcn_readfirstlane(nbp[k]);
+      off[k] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+    });
+    const char *__restrict__ srcb = (const char *)a.src[wl];
+    char *__restrict__ dstb = (char *)a.dst[wl] + (size_t)w.brick * brick_bytes<D, ST>();
     const T beta = T(L.beta);
     double fd[3] = {0, 0, 0};
-    auto boff = [&](int code) { return s_off[code]; };
+    auto boff = [&](int code) {
+      const int nb = nbp[code];
+      return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+    };
     for (int n = threadIdx.x; n < BN; n += blockDim.x) {
       const uint8_t cls = L.cls[(size_t)w.brick * BN + n];
-      if ((cls & CLS_MODE) < w.thr) continue;
+      if ((cls & CLS_MODE) < wthr) continue;
       int x, y, z;
       node_xyz<D>(n, x, y, z);
-      const Lane<D> ln(x, y, z);
+      if (D == 3) z = __builtin_amdgcn_readfirstlane(z);  // one z-slice per wavefront
       T h[Q];
       uint32_t mask = 0;
       if (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) {
         mask = L.mask[(size_t)w.brick * BN + n];
+        const Lane<D> ln(x, y, z);
         pull_special<D, ST>(srcb, boff, ln, n, cls, mask, L, h);
       } else {
-        pull_plain<D, ST>(srcb, boff, ln, h);
+        const BulkLane<D> bl(x, y, z);
+        pull_bulk<D, ST>(srcb, off, bl, h);
       }
       T F[3];
       node_force<D, T>(L, w.brick, n, F);
       const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
-      S *o = dst + n;
-      const T g = kbc_collide<D, T>(h, beta, F, hf, [&](int i, T v) { C::st(o + i * BN, v, T(wgt<D>(i))); });
+      const T g = kbc_collide<D, T>(h, beta, F, hf, [&](int i, T v) {
+        C::st((S *)(dstb + (uint32_t)((i * BN + n) * (int)sizeof(S))), v, T(wgt<D>(i)));
+      });
       if (L.gamma) L.gamma[(size_t)w.brick * BN + n] = (float)g;
       if (cls & CLS_DRAG) {
         // population i leaves towards x + c_i; that node is solid when population Q-1-i
         // bounced back: momentum exchange 2 c_i f'_i, from the values just stored
         for (int i = 0; i < Q; ++i) {
           if (!((mask >> (Q - 1 - i)) & 1u)) continue;
-          const double fi = wgt<D>(i) + (double)C::ld(o + i * BN, T(wgt<D>(i)));
+          const double fi =
+              wgt<D>(i) + (double)C::ld((const S *)(dstb + (uint32_t)((i * BN + n) * (int)sizeof(S))), T(wgt<D>(i)));
           fd[0] += 2.0 * (double)cxo(i) * fi;
           fd[1] += 2.0 * (double)cyo(i) * fi;
           fd[2] += 2.0 * (double)czo<D>(i) * fi;
         }
       }
     }
-    if (w.drag) {  // deterministic block reduction of the momentum exchange
+    if (wdrag) {  // deterministic block reduction of the momentum exchange
       double v[3] = {fd[0], fd[1], fd[2]};
 #pragma unroll
       for (int k = 0; k < 3; ++k)
@@ -443,7 +112,6 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
 // ---------------------------------------------------------------- interface gather
 // Post-stream (rho - 1, u, f^neq) at coarse-aligned interpolation points, parent
 // values brought to child scale (Eq. f_neq_rescaling_iso); one staged row per point.
-template <int D> __host__ __device__ constexpr int stage_width() { return D == 3 ? 32 : 12; }
 
 template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
   using C = Codec<ST>;
@@ -483,78 +151,98 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherA
 // f^neq from staged rows, f = f^eq(rho~, u~) + f~neq; coarse ring nodes: co-located
 // fine post-stream state with f^neq brought to coarse scale.  Both then collide with
 // their own level's parameters (Sec. III.C steps 3-5).
-template <typename T> struct V4;
-template <> struct V4<float> {
-  typedef float type __attribute__((ext_vector_type(4)));
-};
-template <> struct V4<double> {
-  typedef double type __attribute__((ext_vector_type(4)));
-};
+// Fine interface nodes are processed per tile (one workgroup per fine brick): the
+// staged rows its stencils use are copied to LDS once, then every node accumulates
+// its tensor stencil from LDS.  Ring nodes are handled by the trailing workgroups.
+constexpr int COUPLE_LDS_BYTES = 48 * 1024;
+template <int D, typename T> __host__ __device__ constexpr int couple_rows() {
+  return COUPLE_LDS_BYTES / (stage_width<D>() * (int)sizeof(T));
+}
 
-template <int D, int ST> __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
+template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &a, const CItem &c,
+                                                             typename Codec<ST>::T (&h)[nq<D>()]) {
   using C = Codec<ST>;
   using S = typename C::S;
   using T = typename C::T;
-  using V = typename V4<T>::type;
   constexpr int Q = nq<D>();
-  constexpr int SW = stage_width<D>();
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
-  const CItem c = a.items[t];
   const LevelStatic &L = a.lev[c.level];
-  T h[Q];
-  if (c.kind == 0) {
-    T acc[SW];
-#pragma unroll
-    for (int v = 0; v < SW; ++v) acc[v] = 0;
-    const T *stage = (const T *)a.stage;
-    for (int e = c.a; e < c.a + c.b; ++e) {
-      const StencilEntry s = a.sten[e];
-      const T w = T(s.w);
-      const V *row = (const V *)(stage + (size_t)s.slot * SW);
-#pragma unroll
-      for (int v = 0; v < SW / 4; ++v) {
-        const V r = row[v];
-        acc[4 * v + 0] = fma(w, r.x, acc[4 * v + 0]);
-        acc[4 * v + 1] = fma(w, r.y, acc[4 * v + 1]);
-        acc[4 * v + 2] = fma(w, r.z, acc[4 * v + 2]);
-        acc[4 * v + 3] = fma(w, r.w, acc[4 * v + 3]);
-      }
-    }
-    T u[3] = {acc[1], acc[2], D == 3 ? acc[3] : T(0)};
-    T q[Q];
-    eq_dev<D, T>(acc[0], u, q);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) h[i] = acc[1 + D + i] + T(wgt<D>(i)) * q[i];
-  } else {
-    const int fl = c.level + 1;
-    const LevelStatic &Lf = a.lev[fl];
-    const char *srcb = (const char *)a.src[fl];
-    const int32_t *nb = Lf.nbr + (size_t)c.a * 27;
-    auto boff = [&](int code) { return (uint32_t)nb[code] * brick_bytes<D, ST>(); };
-    int x, y, z;
-    node_xyz<D>(c.b, x, y, z);
-    const Lane<D> ln(x, y, z);
-    pull_plain<D, ST>(srcb, boff, ln, h);
-    T drho, j[3];
-    moments<D, T>(h, drho, j);
-    const T ir = rcp(T(1) + drho);
-    T u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
-    T q[Q];
-    eq_dev<D, T>(drho, u, q);
-    const T fac = T(a.pairs[c.level].fac_cp);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T heq = T(wgt<D>(i)) * q[i];
-      h[i] = heq + fac * (h[i] - heq);
-    }
-  }
   T F[3];
   node_force<D, T>(L, c.brick, c.node, F);
   const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
   S *o = (S *)a.dst[c.level] + (size_t)c.brick * Q * BN + c.node;
   const T g = kbc_collide<D, T>(h, T(L.beta), F, hf, [&](int i, T v) { C::st(o + i * BN, v, T(wgt<D>(i))); });
   if (L.gamma) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
+}
+
+template <int D, int ST> __global__ __launch_bounds__(64) void k_couple(CoupleArgs a) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  using V = typename V4<T>::type;
+  constexpr int Q = nq<D>();
+  constexpr int SW = stage_width<D>();
+  extern __shared__ __align__(16) unsigned char couple_lds[];
+  T *rows = (T *)couple_lds;
+  if ((int)blockIdx.x < a.n_tiles) {
+    const CTile t = a.tiles[blockIdx.x];
+    const V *stage = (const V *)a.stage;
+    for (int k = threadIdx.x; k < t.npt * (SW / 4); k += blockDim.x) {
+      const int r = k / (SW / 4), q = k - r * (SW / 4);
+      ((V *)rows)[k] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < t.nitem; it += blockDim.x) {
+      const CItem c = a.items[t.item0 + it];
+      T acc[SW];
+#pragma unroll
+      for (int v = 0; v < SW; ++v) acc[v] = 0;
+      for (int e = c.a; e < c.a + c.b; ++e) {
+        const StencilEntry s = a.sten[e];
+        const T w = T(s.w);
+        const V *row = (const V *)(rows + s.slot * SW);
+#pragma unroll
+        for (int v = 0; v < SW / 4; ++v) {
+          const V r = row[v];
+          acc[4 * v + 0] = fma(w, r.x, acc[4 * v + 0]);
+          acc[4 * v + 1] = fma(w, r.y, acc[4 * v + 1]);
+          acc[4 * v + 2] = fma(w, r.z, acc[4 * v + 2]);
+          acc[4 * v + 3] = fma(w, r.w, acc[4 * v + 3]);
+        }
+      }
+      T u[3] = {acc[1], acc[2], D == 3 ? acc[3] : T(0)};
+      T q[Q], h[Q];
+      eq_dev<D, T>(acc[0], u, q);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) h[i] = acc[1 + D + i] + T(wgt<D>(i)) * q[i];
+      couple_finish<D, ST>(a, c, h);
+    }
+    return;
+  }
+  const int t = ((int)blockIdx.x - a.n_tiles) * blockDim.x + threadIdx.x;
+  if (t >= a.n_ring) return;
+  const CItem c = a.ring[t];
+  const int fl = c.level + 1;
+  const LevelStatic &Lf = a.lev[fl];
+  const char *srcb = (const char *)a.src[fl];
+  const int32_t *nb = Lf.nbr + (size_t)c.a * 27;
+  auto boff = [&](int code) { return (uint32_t)nb[code] * brick_bytes<D, ST>(); };
+  int x, y, z;
+  node_xyz<D>(c.b, x, y, z);
+  const Lane<D> ln(x, y, z);
+  T h[Q];
+  pull_plain<D, ST>(srcb, boff, ln, h);
+  T drho, j[3];
+  moments<D, T>(h, drho, j);
+  const T ir = rcp(T(1) + drho);
+  T u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
+  T q[Q];
+  eq_dev<D, T>(drho, u, q);
+  const T fac = T(a.pairs[c.level].fac_cp);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T heq = T(wgt<D>(i)) * q[i];
+    h[i] = heq + fac * (h[i] - heq);
+  }
+  couple_finish<D, ST>(a, c, h);
 }
 
 // ---------------------------------------------------------------- initialisation
@@ -784,10 +472,22 @@ int launch_gather(int D, int st, const GatherArgs &a, void *stream) {
   return ck();
 }
 
+int stage_row_width(int D) { return D == 3 ? stage_width<3>() : stage_width<2>(); }
+
+int couple_max_rows(int D, int st) {
+  const bool dbl = st == ST_F64;
+  if (D == 2) return dbl ? couple_rows<2, double>() : couple_rows<2, float>();
+  return dbl ? couple_rows<3, double>() : couple_rows<3, float>();
+}
+
 int launch_couple(int D, int st, const CoupleArgs &a, void *stream) {
-  if (a.n <= 0) return 0;
-  const int grid = (a.n + 127) / 128;
-  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, 128, 0, (hipStream_t)stream>>>(a)));
+  // one wavefront per tile (a tile holds about one brick layer of interface nodes);
+  // LDS sized to the largest tile, so several tiles share a CU
+  const int ring_blocks = (a.n_ring + 63) / 64;
+  const int grid = a.n_tiles + ring_blocks;
+  if (grid <= 0) return 0;
+  const size_t lds = (size_t)a.lds_rows * stage_row_width(D) * (st == ST_F64 ? 8 : 4);
+  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, 64, lds, (hipStream_t)stream>>>(a)));
   return ck();
 }
 
@@ -849,8 +549,6 @@ int launch_force_scatter(int D, float *force, const double *F, int nbricks, cons
   else k_force_scatter<3><<<nbricks, BN, 0, (hipStream_t)stream>>>(force, F, borg, box);
   return ck();
 }
-
-int stage_row_width(int D) { return D == 3 ? stage_width<3>() : stage_width<2>(); }
 
 int launch_zero(void *p, size_t bytes, void *stream) {
   size_t n = bytes / 4;

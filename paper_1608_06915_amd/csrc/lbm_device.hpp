@@ -1,0 +1,484 @@
+// lbm_device.hpp -- device building blocks shared by the forward and adjoint kernels:
+// lattice constants, storage codecs, the equilibrium and KBC collision in shifted
+// variables, and the pull addressing over bricks.
+//
+// All collision arithmetic works on shifted populations h_i = f_i - W_i, with
+// rho = 1 + sum h and j = sum c h, which keeps FP32 rounding relative to the small
+// deviations instead of to f itself.  The equilibrium of Eq. feq_iso is evaluated in
+// an equivalent division-free per-axis form: with s = sqrt(1 + 3u^2) and
+// sig = s - 1 = 3u^2 / (1 + s),
+//   (2 - s) ((2u + s)/(1 - u))^c = 1 - sig        (c = 0)
+//                                = 1 + 3cu + 2 sig (c = +-1),
+// (multiply out (2-s)(2u+s) - (1-u) = (1-u)(3u + 2 sig)), so f_i^eq = rho W_i prod_a phi_a
+// and f_i^eq - W_i = W_i q_i with q_i = (1 + drho) prod_a (1 + a_a) - 1 accumulated as
+// q <- q + a + q a.  The inverse equilibrium for the entropic scalar product is the
+// product of per-axis reciprocals (3 per axis instead of one per population).
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "elbm_dev.hpp"
+
+namespace elbm {
+
+
+// ---------------------------------------------------------------- lattice constants
+__host__ __device__ constexpr int cxo(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cyo(int i) { return (i / 3) % 3 - 1; }
+template <int D> __host__ __device__ constexpr int czo(int i) { return D == 3 ? i / 9 - 1 : 0; }
+template <int D> __host__ __device__ constexpr int nq() { return D == 2 ? 9 : 27; }
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+template <int D> __host__ __device__ constexpr double wgt(int i) {
+  return w1(cxo(i)) * w1(cyo(i)) * (D == 3 ? w1(czo<D>(i)) : 1.0);
+}
+
+// ---------------------------------------------------------------- storage codecs
+template <int ST> struct Codec;
+template <> struct Codec<ST_F64> {
+  typedef double S;
+  typedef double T;
+  __device__ static inline T ld(const S *p, T w) { return *p - w; }
+  __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
+};
+template <> struct Codec<ST_F32> {
+  typedef float S;
+  typedef float T;
+  __device__ static inline T ld(const S *p, T w) { return *p - w; }
+  __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
+};
+template <> struct Codec<ST_F16S> {
+  typedef uint16_t S;
+  typedef float T;
+  __device__ static inline T ld(const S *p, T) { return __half2float(__ushort_as_half(*p)); }
+  __device__ static inline void st(S *p, T h, T) { *p = __half_as_ushort(__float2half_rn(h)); }
+};
+template <> struct Codec<ST_BF16S> {
+  typedef uint16_t S;
+  typedef float T;
+  __device__ static inline T ld(const S *p, T) { return __uint_as_float(((uint32_t)*p) << 16); }
+  __device__ static inline void st(S *p, T h, T) {
+    uint32_t b = __float_as_uint(h);
+    if ((b & 0x7fffffffu) > 0x7f800000u) {
+      *p = (uint16_t)0x7fc0u;
+    } else {
+      b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
+      *p = (uint16_t)(b >> 16);
+    }
+  }
+};
+
+// FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
+// division and square root.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double sqrt_(double x) { return sqrt(x); }
+
+// ---------------------------------------------------------------- balanced sums
+// Sums over the populations are balanced trees over the contributing populations
+// only (selected at compile time), so the dependency chains are log2 deep instead
+// of Q long (instruction-level parallelism per wave).
+enum {
+  P_ALL, P_XP, P_XN, P_YP, P_YN, P_ZP, P_ZN,  // sign of one velocity component
+  P_XZP, P_XZN, P_YZP, P_YZN, P_XYP,          // c_a^2 - c_b^2 = +-1, 2-D c_x^2 - c_y^2
+  P_XYN, P_MXYP, P_MXYN, P_MXZP, P_MXZN,      // 2-D c_x^2 - c_y^2 = -1; c_a c_b = +-1
+  P_MYZP, P_MYZN, P_SHEAR                     // c_y c_z = +-1; shear part nonzero
+};
+template <int D, int P> __host__ __device__ constexpr bool pick(int i) {
+  const int x = cxo(i), y = cyo(i), z = czo<D>(i);
+  switch (P) {
+    case P_ALL: return true;
+    case P_XP: return x == 1;
+    case P_XN: return x == -1;
+    case P_YP: return y == 1;
+    case P_YN: return y == -1;
+    case P_ZP: return z == 1;
+    case P_ZN: return z == -1;
+    case P_XZP: return x * x - z * z == 1;
+    case P_XZN: return x * x - z * z == -1;
+    case P_YZP: return y * y - z * z == 1;
+    case P_YZN: return y * y - z * z == -1;
+    case P_XYP: return x * x - y * y == 1;
+    case P_XYN: return x * x - y * y == -1;
+    case P_MXYP: return x * y == 1;
+    case P_MXYN: return x * y == -1;
+    case P_MXZP: return x * z == 1;
+    case P_MXZN: return x * z == -1;
+    case P_MYZP: return y * z == 1;
+    case P_MYZN: return y * z == -1;
+    case P_SHEAR: return x * x + y * y + z * z == 1 || x * x + y * y + z * z == 2;
+  }
+  return false;
+}
+template <int D, int P> __host__ __device__ constexpr int npick(int lo, int n) {
+  int c = 0;
+  for (int i = lo; i < lo + n; ++i) c += pick<D, P>(i) ? 1 : 0;
+  return c;
+}
+// sum of f(i) over i in [LO, LO+N) with pick<D,P>(i); the range has >= 1 term
+template <int D, int P, int LO, int N, typename T, typename F> __device__ inline T tsel(F f) {
+  if constexpr (N == 1) {
+    return f(LO);
+  } else {
+    constexpr int NL = N / 2;
+    constexpr int cl = npick<D, P>(LO, NL), cr = npick<D, P>(LO + NL, N - NL);
+    if constexpr (cl == 0) return tsel<D, P, LO + NL, N - NL, T>(f);
+    else if constexpr (cr == 0) return tsel<D, P, LO, NL, T>(f);
+    else return tsel<D, P, LO, NL, T>(f) + tsel<D, P, LO + NL, N - NL, T>(f);
+  }
+}
+template <int D, int P, typename T, typename F> __device__ inline T tsum(F f) {
+  return tsel<D, P, 0, nq<D>(), T>(f);
+}
+
+template <int I> struct Ic {
+  static constexpr int value = I;
+};
+// compile-time loop: f(Ic<I>) for I in [B, E); indices are constants before any
+// optimisation pass, so small arrays indexed by them stay in registers
+template <int B, int E, typename F> __device__ inline void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(Ic<B>());
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ---------------------------------------------------------------- equilibrium
+// per-axis a(c) = phi(c) - 1 for c = -1, 0, +1 (index c+1)
+template <typename T> __device__ inline void axis_factors(T u, T a[3]) {
+  T t = T(3) * u * u;
+  T sig = t * rcp(T(1) + sqrt_(T(1) + t));
+  a[0] = T(2) * sig - T(3) * u;
+  a[1] = -sig;
+  a[2] = T(2) * sig + T(3) * u;
+}
+
+// partial products over x and y: qxy[cx+1 + 3(cy+1)] = (1+drho)(1+ax)(1+ay) - 1
+template <typename T> __device__ inline void q_table(T drho, const T (&a)[3][3], T (&qxy)[9]) {
+#pragma unroll
+  for (int cx = 0; cx < 3; ++cx) {
+    const T qx = fma(drho, a[0][cx], drho + a[0][cx]);
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy) qxy[cx + 3 * cy] = fma(qx, a[1][cy], qx + a[1][cy]);
+  }
+}
+// q_i = (1 + drho) prod_a phi_a(c_ia) - 1, so that f_i^eq - W_i = W_i q_i
+template <int D, typename T> __device__ inline T q_of(const T (&qxy)[9], const T (&a)[3][3], int i) {
+  T v = qxy[(cxo(i) + 1) + 3 * (cyo(i) + 1)];
+  if (D == 3) {
+    const T b = a[2][czo<D>(i) + 1];
+    v = fma(v, b, v + b);
+  }
+  return v;
+}
+
+template <int D, typename T> __device__ inline void eq_dev(T drho, const T u[3], T (&q)[nq<D>()]) {
+  T a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  axis_factors(u[0], a[0]);
+  axis_factors(u[1], a[1]);
+  if (D == 3) axis_factors(u[2], a[2]);
+  T qxy[9];
+  q_table(drho, a, qxy);
+#pragma unroll
+  for (int i = 0; i < nq<D>(); ++i) q[i] = q_of<D>(qxy, a, i);
+}
+
+template <int D, typename T> __device__ inline void moments(const T (&h)[nq<D>()], T &drho, T (&j)[3]) {
+  auto v = [&](int i) { return h[i]; };
+  drho = tsum<D, P_ALL, T>(v);
+  j[0] = tsum<D, P_XP, T>(v) - tsum<D, P_XN, T>(v);
+  j[1] = tsum<D, P_YP, T>(v) - tsum<D, P_YN, T>(v);
+  j[2] = D == 3 ? tsum<D, P_ZP, T>(v) - tsum<D, P_ZN, T>(v) : T(0);
+}
+
+// ---------------------------------------------------------------- KBC collision
+// Post-collision h' = h - beta (2 ds + gamma dh) (Eq. f_equations with Eq. f_mirr),
+// gamma from Eq. gamma_min_approx, plus the exact-difference forcing of Sec. III.A.
+// h is overwritten by the deviation d = h - (f^eq - W); the post-collision value of
+// population i is handed to st(i, h'_i).  F: force density in level units.
+template <int D, typename T, typename Store>
+__device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_force, Store st) {
+  constexpr int Q = nq<D>();
+  T drho, j[3];
+  moments<D, T>(h, drho, j);
+  const T ir = rcp(T(1) + drho);
+  const T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
+  T a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  axis_factors(u[0], a[0]);
+  axis_factors(u[1], a[1]);
+  if (D == 3) axis_factors(u[2], a[2]);
+  {
+    T qxy[9];
+    q_table(drho, a, qxy);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) h[i] -= T(wgt<D>(i)) * q_of<D>(qxy, a, i);
+  }
+  // deviatoric second moments of d
+  auto v = [&](int i) { return h[i]; };
+  T N1, N2 = 0, Pxz = 0, Pyz = 0;
+  if constexpr (D == 2) {
+    N1 = tsum<D, P_XYP, T>(v) - tsum<D, P_XYN, T>(v);
+  } else {
+    N1 = tsum<D, P_XZP, T>(v) - tsum<D, P_XZN, T>(v);
+    N2 = tsum<D, P_YZP, T>(v) - tsum<D, P_YZN, T>(v);
+    Pxz = tsum<D, P_MXZP, T>(v) - tsum<D, P_MXZN, T>(v);
+    Pyz = tsum<D, P_MYZP, T>(v) - tsum<D, P_MYZN, T>(v);
+  }
+  const T Pxy = tsum<D, P_MXYP, T>(v) - tsum<D, P_MXYN, T>(v);
+  // shear-part values (natural-moment basis, trace in h)
+  T sX, sY, sZ = 0;
+  if (D == 2) {
+    sX = T(0.25) * N1;
+    sY = -T(0.25) * N1;
+  } else {
+    const T s6 = T(1.0 / 6.0);
+    sX = (T(2) * N1 - N2) * s6;
+    sY = (T(2) * N2 - N1) * s6;
+    sZ = -(N1 + N2) * s6;
+  }
+  const T pxy = T(0.25) * Pxy, pxz = T(0.25) * Pxz, pyz = T(0.25) * Pyz;
+  auto dsv = [&](int i) -> T {
+    const int x = cxo(i), y = cyo(i), z = czo<D>(i);
+    const int nz = x * x + y * y + z * z;
+    if (nz == 1) return x ? sX : (y ? sY : sZ);
+    if (nz == 2) return (z == 0) ? T(x * y) * pxy : ((y == 0) ? T(x * z) * pxz : T(y * z) * pyz);
+    return T(0);
+  };
+  // entropic scalar products <ds|dh>, <dh|dh> with weight 1/f^eq = (1/(rho W)) prod 1/phi
+  T A = 0, B = 0;
+  {
+    T rxy[9], rz[3] = {1, 1, 1};
+#pragma unroll
+    for (int cx = 0; cx < 3; ++cx) {
+      const T rx = rcp(T(1) + a[0][cx]);
+#pragma unroll
+      for (int cy = 0; cy < 3; ++cy) rxy[cx + 3 * cy] = rx * rcp(T(1) + a[1][cy]);
+    }
+    if (D == 3)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rz[c] = rcp(T(1) + a[2][c]);
+    auto ifq = [&](int i) -> T {
+      T v = (ir * T(1.0 / wgt<D>(i))) * rxy[(cxo(i) + 1) + 3 * (cyo(i) + 1)];
+      if (D == 3) v *= rz[czo<D>(i) + 1];
+      return v;
+    };
+    A = tsum<D, P_SHEAR, T>([&](int i) {
+      const T ds = dsv(i);
+      return ds * (h[i] - ds) * ifq(i);
+    });
+    B = tsum<D, P_ALL, T>([&](int i) {
+      const T dh = h[i] - dsv(i);
+      return dh * dh * ifq(i);
+    });
+  }
+  const T ib = rcp(beta);
+  T gamma = T(2);
+  if (B > T(0)) {
+    const T g = ib - (T(2) - ib) * (A * rcp(B));
+    if (isfinite(g)) gamma = g;
+  }
+  const T b2 = T(2) * beta, bg = beta * gamma;
+  T qxy[9];
+  q_table(drho, a, qxy);
+  if (has_force) {
+    const T u2[3] = {u[0] + F[0] * ir, u[1] + F[1] * ir, D == 3 ? u[2] + F[2] * ir : T(0)};
+    T a2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    axis_factors(u2[0], a2[0]);
+    axis_factors(u2[1], a2[1]);
+    if (D == 3) axis_factors(u2[2], a2[2]);
+    T qxy2[9];
+    q_table(drho, a2, qxy2);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T ds = dsv(i), d = h[i];
+      const T q = q_of<D>(qxy, a, i);
+      const T q2 = q_of<D>(qxy2, a2, i);
+      st(i, T(wgt<D>(i)) * q2 + (d - b2 * ds - bg * (d - ds)));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T ds = dsv(i), d = h[i];
+      st(i, T(wgt<D>(i)) * q_of<D>(qxy, a, i) + (d - b2 * ds - bg * (d - ds)));
+    }
+  }
+  return gamma;
+}
+
+template <int D, typename T> __device__ inline void node_force(const LevelStatic &L, int brick, int n, T F[3]) {
+  F[0] = T(L.F[0]);
+  F[1] = T(L.F[1]);
+  F[2] = T(L.F[2]);
+  if (L.force) {
+    const float *fp = L.force + (size_t)brick * D * BN + n;
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] += T(fp[a * BN]) * T(L.fscale);
+  }
+}
+
+// ---------------------------------------------------------------- pull streaming
+// Sources are addressed as 32-bit byte offsets from the level's population buffer
+// (an SGPR base): offset = brick_offset[neighbour code] + (i*BN + local node)*size.
+template <int B> __device__ inline int side(int s) { return s < 0 ? 0 : (s >= B ? 2 : 1); }
+
+template <int D> struct Lane {
+  // per source displacement k = c+1 along each axis: neighbour code part, local index part
+  int xb[3], xl[3], yzb[9], yzl[9];
+  __device__ inline Lane(int x, int y, int z) {
+    using Bk = Brick<D>;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int sx = x + 1 - k;
+      xb[k] = side<Bk::BX>(sx);
+      xl[k] = sx & (Bk::BX - 1);
+    }
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kz = 0; kz < 3; ++kz) {
+        const int sy = y + 1 - ky;
+        const int sz = D == 3 ? z + 1 - kz : 0;
+        yzb[ky + 3 * kz] = 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
+        yzl[ky + 3 * kz] = Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
+      }
+  }
+  __device__ inline int code(int i) const {
+    return xb[cxo(i) + 1] + yzb[(cyo(i) + 1) + 3 * (czo<D>(i) + 1)];
+  }
+  __device__ inline int local(int i) const {
+    return xl[cxo(i) + 1] + yzl[(cyo(i) + 1) + 3 * (czo<D>(i) + 1)];
+  }
+};
+
+template <int D, int ST, typename OFF>
+__device__ inline void pull_plain(const char *__restrict__ srcb, OFF boff, const Lane<D> &ln,
+                                  typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+#pragma unroll
+  for (int i = 0; i < nq<D>(); ++i) {
+    const uint32_t off = boff(ln.code(i)) + (uint32_t)((i * BN + ln.local(i)) * (int)sizeof(S));
+    h[i] = C::ld((const S *)(srcb + off), T(wgt<D>(i)));
+  }
+}
+
+template <int D, int ST, typename OFF>
+__device__ inline void pull_special(const char *__restrict__ srcb, OFF boff, const Lane<D> &ln, int n,
+                                    uint8_t cls, uint32_t mask, const LevelStatic &L,
+                                    typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+  using Bk = Brick<D>;
+  constexpr int Q = nq<D>();
+  const uint32_t own = boff(13);
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const bool hit = (mask >> i) & 1u;
+    if (hit && (cls & CLS_LINKS)) {  // halfway bounce-back: own node, opposite velocity
+      h[i] = C::ld((const S *)(srcb + own + (uint32_t)(((Q - 1 - i) * BN + n) * (int)sizeof(S))),
+                   T(wgt<D>(Q - 1 - i)));
+    } else if (hit && (cls & CLS_INLET)) {
+      h[i] = T(L.hin[i]);
+    } else if (hit && (cls & CLS_OUTFLOW)) {  // zero gradient: value one node upstream
+      int x = n & (Bk::BX - 1), y = (n >> Bk::LX) & (Bk::BY - 1), z = D == 3 ? n >> (Bk::LX + Bk::LY) : 0;
+      const int sx = x - cxo(i) - L.oshift[0], sy = y - cyo(i) - L.oshift[1], sz = z - czo<D>(i) - L.oshift[2];
+      const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
+      const int loc =
+          (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
+      h[i] = C::ld((const S *)(srcb + boff(code) + (uint32_t)((i * BN + loc) * (int)sizeof(S))), T(wgt<D>(i)));
+    } else {
+      const uint32_t off = boff(ln.code(i)) + (uint32_t)((i * BN + ln.local(i)) * (int)sizeof(S));
+      h[i] = C::ld((const S *)(srcb + off), T(wgt<D>(i)));
+    }
+  });
+}
+
+template <int D> struct BulkLane {
+  bool xlo, xhi, ylo, yhi;  // per lane: on the low/high x (y) face of the brick
+  int lx[3], ly[3];         // local x, y of the source for c = +1, 0, -1 (index 1 - c)
+  int lz[3];                // local z part (uniform)
+  bool zlo, zhi;            // uniform
+  __device__ inline BulkLane(int x, int y, int z) {
+    using Bk = Brick<D>;
+    xlo = x == 0;
+    xhi = x == Bk::BX - 1;
+    ylo = y == 0;
+    yhi = y == Bk::BY - 1;
+    static_for<0, 3>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      lx[k] = (x - 1 + k) & (Bk::BX - 1);
+      ly[k] = Bk::BX * ((y - 1 + k) & (Bk::BY - 1));
+      lz[k] = D == 3 ? Bk::BX * Bk::BY * ((z - 1 + k) & (Bk::BZ - 1)) : 0;
+    });
+    zlo = D == 3 && z == 0;
+    zhi = D == 3 && z == Bk::BZ - 1;
+  }
+};
+
+template <int D, int ST>
+__device__ inline void pull_bulk(const char *__restrict__ srcb, const uint32_t (&off)[27], const BulkLane<D> &b,
+                                 typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+  // z-plane of the source per direction (uniform): cz = +1 -> low neighbour when on
+  // the low face, cz = -1 -> high neighbour when on the high face
+  uint32_t oz[3][9];
+  static_for<0, 9>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    oz[0][k] = b.zlo ? off[k] : off[k + 9];
+    oz[1][k] = off[k + 9];
+    oz[2][k] = b.zhi ? off[k + 18] : off[k + 9];
+  });
+  static_for<0, nq<D>()>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
+    constexpr int kz = 1 - cz;
+    // the candidates are wave-uniform; readfirstlane keeps them scalar values so the
+    // per-lane choice stays a register select (not an indexed load)
+    auto U = [&](int k) -> uint32_t { return __builtin_amdgcn_readfirstlane(oz[kz][k]); };
+    auto Ox = [&](auto BY) -> uint32_t {
+      constexpr int by = decltype(BY)::value;
+      if constexpr (cx == 1) return b.xlo ? U(0 + 3 * by) : U(1 + 3 * by);
+      else if constexpr (cx == -1) return b.xhi ? U(2 + 3 * by) : U(1 + 3 * by);
+      else return U(1 + 3 * by);
+    };
+    uint32_t base;
+    if constexpr (cy == 1) base = b.ylo ? Ox(Ic<0>()) : Ox(Ic<1>());
+    else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
+    else base = Ox(Ic<1>());
+    const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
+    h[i] = C::ld((const S *)(srcb + base + (uint32_t)((i * BN + loc) * (int)sizeof(S))), T(wgt<D>(i)));
+  });
+}
+
+template <int D> __device__ inline void node_xyz(int n, int &x, int &y, int &z) {
+  using Bk = Brick<D>;
+  x = n & (Bk::BX - 1);
+  y = (n >> Bk::LX) & (Bk::BY - 1);
+  z = D == 3 ? (n >> (Bk::LX + Bk::LY)) : 0;
+}
+
+__device__ inline int xcd_perm(int b, int G) {
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range
+  return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+template <int D, int ST> __device__ constexpr uint32_t brick_bytes() {
+  return (uint32_t)(nq<D>() * BN * sizeof(typename Codec<ST>::S));
+}
+
+template <int D> __host__ __device__ constexpr int stage_width() { return D == 3 ? 32 : 12; }
+
+template <typename T> struct V4;
+template <> struct V4<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <> struct V4<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+
+
+}  // namespace elbm

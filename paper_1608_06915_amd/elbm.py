@@ -30,7 +30,7 @@ EXPORTS = [
     "elbm_node_class", "elbm_weights", "elbm_bind", "elbm_init_fields", "elbm_set_force_field", "elbm_advance",
     "elbm_read_moments", "elbm_read_populations", "elbm_sample_populations", "elbm_reduce", "elbm_check",
     "elbm_drag", "elbm_set_gamma_output", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
-    "elbm_state_bytes", "elbm_save_state", "elbm_load_state",
+    "elbm_state_bytes", "elbm_save_state", "elbm_load_state", "elbm_get_launch",
 ]
 
 
@@ -83,6 +83,7 @@ def lib():
             "elbm_set_gamma_output": [P, i32],
             "elbm_set_launch": [P, i32, i32, i32, i32, i32],
             "elbm_tune": [P, ctypes.c_char_p, i32],
+            "elbm_get_launch": [P, P],
             "elbm_profile": [P, i32, dp, dp, i64p],
             "elbm_synchronize": [P],
             "elbm_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
@@ -294,6 +295,11 @@ class Lattice:
     def set_launch(self, use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, occupancy=1):
         self._ck(lib().elbm_set_launch(self._h, int(use_graph), int(wg_per_cu), int(xcd_remap), int(threads),
                                        int(occupancy)))
+
+    def get_launch(self):
+        cfg = (ctypes.c_int32 * 5)()
+        self._ck(lib().elbm_get_launch(self._h, cfg))
+        return dict(zip(("use_graph", "wg_per_cu", "xcd_remap", "threads", "occupancy"), list(cfg)))
 
     def tune(self, cache_path=None, steps=3):
         self._ck(lib().elbm_tune(self._h, cache_path.encode() if cache_path else None, int(steps)))
