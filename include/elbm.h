@@ -110,8 +110,9 @@ elbm_status elbm_set_force_uniform(elbm_ctx *ctx, const double F[3]);
 elbm_status elbm_finalize(elbm_ctx *ctx, size_t *workspace_bytes);
 
 elbm_status elbm_level_box(const elbm_ctx *ctx, int level, int64_t lo[3], int64_t n[3]);
-/* Node counts: n_nodes (stored nodes incl. solid), n_fluid, n_update (fluid nodes
- * updated per level step), relaxation parameter beta_l (Eq. visc), bricks. */
+/* Node counts: n_nodes (stored nodes incl. solid), n_fluid (nodes that collide every
+ * level step, interface layers included), relaxation parameter beta_l (Eq. visc),
+ * number of bricks. */
 elbm_status elbm_level_info(const elbm_ctx *ctx, int level, int64_t *n_nodes, int64_t *n_fluid, double *beta,
                             int64_t *n_bricks);
 /* Node classes over the level index box (int32): -1 absent, else bit0 solid, bit1
@@ -190,6 +191,56 @@ elbm_status elbm_synchronize(elbm_ctx *ctx);
 elbm_status elbm_state_bytes(const elbm_ctx *ctx, size_t *bytes);
 elbm_status elbm_save_state(elbm_ctx *ctx, void *dev_dst);
 elbm_status elbm_load_state(elbm_ctx *ctx, const void *dev_src);
+
+/* ---- Discrete adjoint.  The paper has no adjoint: this is the exact transpose of the
+ * linearised coarse step that elbm_advance computes (collision of Sec. II.A with the
+ * stabiliser of Eq. gamma_min_approx and the exact-difference forcing of Sec. III.A,
+ * the rescaling Eq. f_neq_rescaling_iso and reconstruction Eq. interp of Sec. III, and
+ * streaming, in the order of the Sec. III.C schedule).  Where <dh|dh> = 0 the
+ * stabiliser is the constant 2 and is not differentiated; the collision is not
+ * differentiable at equilibrium, so gradients are meaningful at non-equilibrium
+ * states.  Half-precision storage is differentiated as if rounding were the
+ * identity.  Adjoint arithmetic uses the compute type of the storage (FP64 for
+ * ELBM_F64, else FP32).
+ *
+ * Objectives:
+ *   ELBM_OBJ_DRAG  J = dir . (sum over the run's substeps of level body_level of the
+ *                  momentum exchange 2 c_i f'_i on solid links) / number of substeps;
+ *   ELBM_OBJ_KE    J = 1/2 sum_l sum_x w |j - F/2|^2 / rho at the final state, w the
+ *                  owned-volume weights of elbm_weights. */
+typedef enum { ELBM_OBJ_DRAG = 0, ELBM_OBJ_KE = 1 } elbm_objective;
+
+/* Device workspace for runs of up to n_max coarse steps with a checkpoint every K
+ * coarse steps: ceil(n_max/K) checkpointed states, a tape of K 2^l + 1 states per
+ * level l for the recomputed segment, and the adjoint fields.  After elbm_finalize. */
+elbm_status elbm_adjoint_bytes(elbm_ctx *ctx, int n_max, int K, size_t *bytes);
+/* Bind the caller-owned adjoint workspace (256-byte aligned, at least the size above;
+ * never freed by the library).  After elbm_bind. */
+elbm_status elbm_adjoint_bind(elbm_ctx *ctx, void *workspace_dev, size_t bytes, int n_max, int K);
+/* Advance n coarse steps (1 <= n <= n_max) from the current state as elbm_advance
+ * does, checkpointing every K steps, and evaluate J (written to *J).  The state
+ * afterwards is the final state.  For ELBM_OBJ_DRAG the drag accumulators of
+ * body_level are reset before and after.  Synchronous. */
+elbm_status elbm_adjoint_forward(elbm_ctx *ctx, int n, int objective, int body_level, const double dir[3],
+                                 double *J);
+/* Reverse sweep of the preceding elbm_adjoint_forward: segment by segment the forward
+ * is recomputed from its checkpoint, then its ticks are reversed.  The state, force
+ * fields and geometry must not change in between (not checked).  The forward state is
+ * left unchanged.  Synchronous. */
+elbm_status elbm_adjoint_backward(elbm_ctx *ctx);
+/* Results of elbm_adjoint_backward for one level, device arrays over the level box:
+ * lam [Q][box] = dJ/df of the state at the start of the forward run, dJdF [D][box] =
+ * dJ/dF for the per-node force field of elbm_set_force_field (level-0 units).  Zero
+ * at absent and solid nodes.  Either pointer may be NULL.  Asynchronous. */
+elbm_status elbm_adjoint_read(elbm_ctx *ctx, int level, double *lam_dev, double *dJdF_dev);
+/* dJ/du0 [D][box] (host) through the initialisation f = f^eq(rho0, u0) (1 + noise) of
+ * elbm_init_fields, given the same host arrays that initialised the level.
+ * Synchronous. */
+elbm_status elbm_adjoint_velocity(elbm_ctx *ctx, int level, const double *rho_host, const double *u_host,
+                                  const double *noise_host, double *out_host);
+/* Milliseconds of the last adjoint run: forward with checkpoints, recomputation,
+ * reverse ticks. */
+elbm_status elbm_adjoint_timing(const elbm_ctx *ctx, double ms[3]);
 
 #ifdef __cplusplus
 }

@@ -128,6 +128,26 @@ struct elbm_ctx {
   bool gamma_on = false;
   bool timing = false;
   std::vector<hipEvent_t> tev;
+  std::vector<std::pair<size_t, size_t>> pair_gp;  // interpolation points of each pair (offset, count)
+  // discrete adjoint
+  struct Adjoint {
+    bool bound = false, pending = false;
+    char *ws = nullptr;
+    int nmax = 0, K = 1;
+    size_t o_tape[MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL] = {}, o_lF[MAXL] = {},
+           o_amask[MAXL] = {}, o_alev = 0, o_astage = 0, o_tofs = 0, o_tsten = 0, o_items = 0, o_part = 0,
+           o_res = 0, need = 0;
+    bool has_amask[MAXL] = {};
+    std::vector<WorkItem> items;                  // every brick of the arriving levels, per tick
+    std::vector<std::pair<size_t, size_t>> tick;  // (offset, count) into items per tick
+    std::vector<int32_t> tofs;
+    std::vector<StencilEntry> tsten;
+    std::vector<uint32_t> amask[MAXL];
+    int cur[MAXL] = {};  // lam buffer holding the adjoint of the current state
+    int n = 0, objective = 0, body_level = -1;
+    double dir[3] = {0, 0, 0}, J = 0;
+    float ms[3] = {0, 0, 0};  // forward with checkpoints, recomputation, reverse sweep
+  } adj;
   int cu_count = 256;
 };
 
@@ -856,6 +876,8 @@ void build_schedule(elbm_ctx *c) {
   gp_start[pL] = c->gp_all.size();
   tl_start[pL] = c->tiles_all.size();
   rg_start[pL] = c->ring_all.size();
+  c->pair_gp.assign(c->pairs.size(), std::pair<size_t, size_t>(0, 0));
+  for (size_t p = 0; p < c->pairs.size(); ++p) c->pair_gp[p] = {gp_start[p], gp_start[p + 1] - gp_start[p]};
   const int T = 1 << (c->L - 1);
   for (int t = 1; t <= T; ++t) {
     int lmin = c->L - 1;
@@ -992,15 +1014,10 @@ void invalidate_graphs(elbm_ctx *c) {
 // buffer index of level l at its k-th step (1-based) of a coarse step with level-0 parity p
 int src_index(int l, int p, int k) { return ((l == 0 ? p : 0) ^ ((k - 1) & 1)); }
 
-elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_t side, bool fork) {
+// one tick with explicit input/output buffers per level (flags: FL_DRAG, FL_GAMMA)
+elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *const dst[MAXL], hipStream_t main,
+                            hipStream_t side, bool fork, int flags) {
   const Tick &tk = c->ticks[t - 1];
-  void *src[MAXL] = {}, *dst[MAXL] = {};
-  for (int l = tk.lmin; l < c->L; ++l) {
-    const int k = t >> (c->L - 1 - l);
-    const int si = src_index(l, p, k);
-    src[l] = c->ws + c->lev[l].o_pop[si];
-    dst[l] = c->ws + c->lev[l].o_pop[si ^ 1];
-  }
   const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
   const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
   const bool coupling = tk.tile_n + tk.ring_n > 0;
@@ -1038,12 +1055,16 @@ elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_
       a.src[l] = src[l];
       a.dst[l] = dst[l];
     }
+    a.flags = flags;
+    a.pad = 0;
     LCK(c, launch_couple(c->D, c->storage, a, cs));
   }
   SCArgs s;
   s.items = (const WorkItem *)(c->ws + c->o_sc) + tk.sc_off;
   s.n_items = (int)tk.sc_n;
   s.remap = c->xcd_remap;
+  s.flags = flags;
+  s.pad = 0;
   s.lev = lev;
   for (int l = 0; l < MAXL; ++l) {
     s.src[l] = src[l];
@@ -1071,6 +1092,18 @@ elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_
     HIPCK(c, hipStreamWaitEvent(main, ej, 0));
   }
   return ELBM_OK;
+}
+
+elbm_status enqueue_tick(elbm_ctx *c, int t, int p, hipStream_t main, hipStream_t side, bool fork) {
+  const Tick &tk = c->ticks[t - 1];
+  void *src[MAXL] = {}, *dst[MAXL] = {};
+  for (int l = tk.lmin; l < c->L; ++l) {
+    const int k = t >> (c->L - 1 - l);
+    const int si = src_index(l, p, k);
+    src[l] = c->ws + c->lev[l].o_pop[si];
+    dst[l] = c->ws + c->lev[l].o_pop[si ^ 1];
+  }
+  return enqueue_tick_io(c, t, src, dst, main, side, fork, FL_DRAG | FL_GAMMA);
 }
 
 elbm_status enqueue_coarse_step(elbm_ctx *c, int p, hipStream_t main, hipStream_t side, bool fork) {
@@ -1105,6 +1138,232 @@ elbm_status build_graphs(elbm_ctx *c) {
 elbm_status check_level(const elbm_ctx *c, int level) {
   if (!c->finalized) return ELBM_ESTATE;
   if (level < 0 || level >= c->L) return ELBM_EINVAL;
+  return ELBM_OK;
+}
+
+
+// ---------------------------------------------------------------- discrete adjoint (host)
+// Reverse sweep of the coarse step: segments of K coarse steps are recomputed from
+// checkpoints into a tape of per-substep states (one slot per level substep), then
+// the ticks are reversed one by one (kernels in adjoint.hip).
+
+void adj_build_tables(elbm_ctx *c) {
+  auto &A = c->adj;
+  A.items.clear();
+  A.tick.clear();
+  const int T = 1 << (c->L - 1);
+  for (int t = 1; t <= T; ++t) {
+    const int lmin = c->ticks[t - 1].lmin;
+    const size_t off = A.items.size();
+    for (int l = lmin; l < c->L; ++l)
+      for (int32_t b = 0; b < c->lev[l].nb; ++b) {
+        WorkItem w;
+        w.brick = b;
+        w.level = (uint8_t)l;
+        w.thr = (uint8_t)((l == lmin && l > 0) ? 1 : 2);
+        w.drag = 0;
+        w.pad = 0;
+        A.items.push_back(w);
+      }
+    A.tick.push_back({off, A.items.size() - off});
+  }
+  // transposed interpolation stencils: per staged row, the fine items reading it
+  const int ncols = std::max(c->stage_cols, 1);
+  std::vector<std::vector<StencilEntry>> by((size_t)ncols);
+  for (const CTile &t : c->tiles_all)
+    for (int32_t k = 0; k < t.nitem; ++k) {
+      const int32_t item = t.item0 + k;
+      const CItem &it = c->fine_all[(size_t)item];
+      for (int32_t e = it.a; e < it.a + it.b; ++e) {
+        const StencilEntry &se = c->tsten_all[(size_t)e];
+        StencilEntry o;
+        o.slot = item;
+        o.w = se.w;
+        by[(size_t)c->tile_rows_all[(size_t)(t.pt0 + se.slot)]].push_back(o);
+      }
+    }
+  A.tofs.assign((size_t)ncols + 1, 0);
+  A.tsten.clear();
+  for (int k = 0; k < ncols; ++k) {
+    A.tofs[(size_t)k] = (int32_t)A.tsten.size();
+    A.tsten.insert(A.tsten.end(), by[(size_t)k].begin(), by[(size_t)k].end());
+  }
+  A.tofs[(size_t)ncols] = (int32_t)A.tsten.size();
+  // populations that outflow nodes copy from their upstream neighbour
+  int outflow = -1;
+  for (int f = 0; f < 6; ++f)
+    if (c->face_kind[f] == ELBM_FACE_OUTFLOW) outflow = f;
+  for (int l = 0; l < c->L; ++l) {
+    A.has_amask[l] = false;
+    A.amask[l].clear();
+  }
+  if (outflow < 0) return;
+  int64_t osh[3] = {0, 0, 0};
+  osh[outflow / 2] = (outflow & 1) ? 1 : -1;
+  for (int l = 0; l < c->L; ++l) {
+    const Level &L = c->lev[l];
+    A.amask[l].assign((size_t)L.nb * BN, 0u);
+    for (int32_t b = 0; b < L.nb; ++b)
+      for (int n = 0; n < BN; ++n) {
+        const size_t k = (size_t)b * BN + n;
+        if (!(L.cls[k] & CLS_FLUID)) continue;
+        const int64_t loc[3] = {n % bdim(c->D, 0), (n / bdim(c->D, 0)) % bdim(c->D, 1),
+                                n / (bdim(c->D, 0) * bdim(c->D, 1))};
+        for (int i = 0; i < c->Q; ++i) {
+          int64_t y[3];
+          for (int a = 0; a < 3; ++a) y[a] = L.blo[a] + L.borg[3 * b + a] + loc[a] + vel(c->D, i, a) + osh[a];
+          NodeRef r = locate(c, l, y);
+          if (r.brick < 0) continue;
+          const size_t m = (size_t)r.brick * BN + r.node;
+          if ((L.cls[m] & CLS_OUTFLOW) && ((L.mask[m] >> i) & 1u)) A.amask[l][k] |= 1u << i;
+        }
+        if (A.amask[l][k]) A.has_amask[l] = true;
+      }
+  }
+}
+
+size_t level_state_bytes(const elbm_ctx *c, int l) {
+  return (size_t)c->lev[l].nb * c->Q * BN * store_bytes(c->storage);
+}
+
+void adj_layout(elbm_ctx *c, int nmax, int K) {
+  auto &A = c->adj;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  const size_t tb = comp_bytes(c->storage);
+  size_t state = 0;
+  for (int l = 0; l < c->L; ++l) {
+    A.o_tape[l] = take(level_state_bytes(c, l) * ((size_t)K * ((size_t)1 << l) + 1));
+    state += level_state_bytes(c, l);
+  }
+  const size_t S = (size_t)((nmax + K - 1) / K);
+  A.o_ckpt = take(S * state);
+  for (int l = 0; l < c->L; ++l) {
+    const size_t nb = (size_t)c->lev[l].nb;
+    A.o_lam[l][0] = take(nb * c->Q * BN * tb);
+    A.o_lam[l][1] = take(nb * c->Q * BN * tb);
+    A.o_lg[l] = take((nb + 1) * c->Q * BN * tb);
+    A.o_lF[l] = take(nb * c->D * BN * tb);
+    A.o_amask[l] = take(A.has_amask[l] ? nb * BN * 4 : 0);
+  }
+  A.o_alev = take(sizeof(AdjLevel) * MAXL);
+  A.o_astage = take(c->fine_all.size() * stage_row_width(c->D) * tb);
+  A.o_tofs = take(A.tofs.size() * 4);
+  A.o_tsten = take(A.tsten.size() * sizeof(StencilEntry));
+  A.o_items = take(A.items.size() * sizeof(WorkItem));
+  A.o_part = take(c->red_items.size() * 5 * 8);
+  A.o_res = take(64);
+  A.need = off;
+}
+
+char *adj_tape(elbm_ctx *c, int l, size_t slot) {
+  return c->adj.ws + c->adj.o_tape[l] + slot * level_state_bytes(c, l);
+}
+
+char *adj_ckpt(elbm_ctx *c, int s, int l) {
+  size_t state = 0, before = 0;
+  for (int q = 0; q < c->L; ++q) {
+    if (q < l) before += level_state_bytes(c, q);
+    state += level_state_bytes(c, q);
+  }
+  return c->adj.ws + c->adj.o_ckpt + (size_t)s * state + before;
+}
+
+char *cur_state(elbm_ctx *c, int l) { return c->ws + c->lev[l].o_pop[l == 0 ? c->parity : 0]; }
+
+// reverse of tick t of coarse step k (1-based) of the current segment
+elbm_status adj_tick(elbm_ctx *c, int k, int t) {
+  auto &A = c->adj;
+  const Tick &tk = c->ticks[t - 1];
+  const int L = c->L;
+  void *src[MAXL] = {}, *lamd[MAXL] = {}, *lams[MAXL] = {}, *lg[MAXL] = {}, *lF[MAXL] = {};
+  for (int l = 0; l < L; ++l) {
+    lg[l] = A.ws + A.o_lg[l];
+    lF[l] = A.ws + A.o_lF[l];
+  }
+  for (int l = tk.lmin; l < L; ++l) {
+    const int m = t >> (L - 1 - l);
+    src[l] = adj_tape(c, l, ((size_t)(k - 1) << l) + (size_t)(m - 1));
+    lamd[l] = A.ws + A.o_lam[l][A.cur[l]];
+    lams[l] = A.ws + A.o_lam[l][A.cur[l] ^ 1];
+  }
+  const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
+  const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
+  AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  a.items = (const WorkItem *)(A.ws + A.o_items) + A.tick[(size_t)t - 1].first;
+  a.n_items = (int)A.tick[(size_t)t - 1].second;
+  a.drag_level = A.objective == ELBM_OBJ_DRAG ? A.body_level : -1;
+  if (A.objective == ELBM_OBJ_DRAG) {
+    const double nsub = (double)A.n * (double)((int64_t)1 << A.body_level);
+    for (int q = 0; q < 3; ++q) a.drag_seed[q] = A.dir[q] / nsub;
+  }
+  a.lev = lev;
+  a.alev = (const AdjLevel *)(A.ws + A.o_alev);
+  for (int l = 0; l < MAXL; ++l) {
+    a.src[l] = src[l];
+    a.lam[l] = lamd[l];
+    a.lg[l] = lg[l];
+    a.lF[l] = lF[l];
+  }
+  LCK(c, launch_adj_collide(c->D, c->storage, a, c->stream));
+  if (tk.tile_n + tk.ring_n > 0) {
+    GatherArgs g;
+    g.pts = (const GPoint *)(c->ws + c->o_gp) + tk.gp_off;
+    g.n = (int)tk.gp_n;
+    g.stride = stage_row_width(c->D);
+    g.stage = c->ws + c->o_stage;
+    g.lev = lev;
+    g.pairs = pairs;
+    for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
+    LCK(c, launch_gather(c->D, c->storage, g, c->stream));
+    AdjCoupleArgs ca;
+    memset(&ca, 0, sizeof(ca));
+    ca.c.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
+    ca.c.n_tiles = (int)tk.tile_n;
+    ca.c.lds_rows = c->lds_rows;
+    ca.c.tile_rows = (const int32_t *)(c->ws + c->o_trows);
+    ca.c.items = (const CItem *)(c->ws + c->o_fine);
+    ca.c.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;
+    ca.c.n_ring = (int)tk.ring_n;
+    ca.c.stride = stage_row_width(c->D);
+    ca.c.sten = (const StencilEntry *)(c->ws + c->o_sten);
+    ca.c.stage = c->ws + c->o_stage;
+    ca.c.lev = lev;
+    ca.c.pairs = pairs;
+    for (int l = 0; l < MAXL; ++l) {
+      ca.c.src[l] = src[l];
+      ca.lam[l] = lamd[l];
+      ca.lg[l] = lg[l];
+      ca.lF[l] = lF[l];
+    }
+    ca.astage = A.ws + A.o_astage;
+    LCK(c, launch_adj_couple(c->D, c->storage, ca, c->stream));
+    // pairs one after the other: a level's points of two pairs may coincide
+    for (int p = tk.lmin; p + 1 < L; ++p) {
+      AdjPointArgs pa;
+      memset(&pa, 0, sizeof(pa));
+      pa.pts = (const GPoint *)(c->ws + c->o_gp) + c->pair_gp[(size_t)p].first;
+      pa.n = (int)c->pair_gp[(size_t)p].second;
+      pa.tofs = (const int32_t *)(A.ws + A.o_tofs);
+      pa.tsten = (const StencilEntry *)(A.ws + A.o_tsten);
+      pa.astage = A.ws + A.o_astage;
+      pa.lev = lev;
+      pa.pairs = pairs;
+      for (int l = 0; l < MAXL; ++l) {
+        pa.src[l] = src[l];
+        pa.lg[l] = lg[l];
+      }
+      LCK(c, launch_adj_points(c->D, c->storage, pa, c->stream));
+    }
+  }
+  for (int l = 0; l < MAXL; ++l) a.lam[l] = lams[l];
+  LCK(c, launch_adj_transpose(c->D, c->storage, a, c->stream));
+  for (int l = tk.lmin; l < L; ++l) A.cur[l] ^= 1;
   return ELBM_OK;
 }
 
@@ -1791,6 +2050,233 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
       fclose(f);
     }
   }
+  return ELBM_OK;
+}
+
+
+// ---------------------------------------------------------------- discrete adjoint
+elbm_status elbm_adjoint_bytes(elbm_ctx *c, int n_max, int K, size_t *bytes) {
+  if (!c || !bytes) return ELBM_EINVAL;
+  if (!c->finalized) FAIL(c, ELBM_ESTATE, "adjoint_bytes before finalize");
+  if (n_max < 1 || K < 1) FAIL(c, ELBM_EINVAL, "adjoint: need n_max >= 1 and K >= 1");
+  adj_build_tables(c);
+  adj_layout(c, n_max, K);
+  *bytes = c->adj.need;
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_bind(elbm_ctx *c, void *ws, size_t bytes, int n_max, int K) {
+  if (!c || !ws) return ELBM_EINVAL;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "adjoint_bind before bind");
+  if (n_max < 1 || K < 1) FAIL(c, ELBM_EINVAL, "adjoint: need n_max >= 1 and K >= 1");
+  if ((uintptr_t)ws & 255) FAIL(c, ELBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+  auto &A = c->adj;
+  adj_build_tables(c);
+  adj_layout(c, n_max, K);
+  if (bytes < A.need) FAIL(c, ELBM_ESMALL, "adjoint workspace %zu bytes < %zu required", bytes, A.need);
+  A.ws = (char *)ws;
+  A.nmax = n_max;
+  A.K = K;
+  A.pending = false;
+  A.n = 0;
+  const size_t tb = comp_bytes(c->storage);
+  AdjLevel al[MAXL];
+  memset(al, 0, sizeof(al));
+  for (int l = 0; l < c->L; ++l) {
+    const size_t nb = (size_t)c->lev[l].nb;
+    al[l].zero_brick = (int32_t)nb;
+    if (A.has_amask[l]) {
+      al[l].amask = (const uint32_t *)(A.ws + A.o_amask[l]);
+      HIPCK(c, hipMemcpy(A.ws + A.o_amask[l], A.amask[l].data(), A.amask[l].size() * 4, hipMemcpyHostToDevice));
+    }
+    LCK(c, launch_zero(A.ws + A.o_lg[l], (nb + 1) * c->Q * BN * tb, c->stream));
+    LCK(c, launch_zero(A.ws + A.o_lam[l][0], nb * c->Q * BN * tb, c->stream));
+    LCK(c, launch_zero(A.ws + A.o_lam[l][1], nb * c->Q * BN * tb, c->stream));
+    LCK(c, launch_zero(A.ws + A.o_lF[l], nb * c->D * BN * tb, c->stream));
+  }
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  HIPCK(c, hipMemcpy(A.ws + A.o_alev, al, sizeof(al), hipMemcpyHostToDevice));
+  if (!A.tofs.empty()) HIPCK(c, hipMemcpy(A.ws + A.o_tofs, A.tofs.data(), A.tofs.size() * 4, hipMemcpyHostToDevice));
+  if (!A.tsten.empty())
+    HIPCK(c, hipMemcpy(A.ws + A.o_tsten, A.tsten.data(), A.tsten.size() * sizeof(StencilEntry),
+                       hipMemcpyHostToDevice));
+  if (!A.items.empty())
+    HIPCK(c, hipMemcpy(A.ws + A.o_items, A.items.data(), A.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  A.bound = true;
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_forward(elbm_ctx *c, int n, int objective, int body_level, const double dir[3],
+                                 double *J) {
+  if (!c) return ELBM_EINVAL;
+  auto &A = c->adj;
+  if (!A.bound) FAIL(c, ELBM_ESTATE, "adjoint_forward before adjoint_bind");
+  if (n < 1 || n > A.nmax) FAIL(c, ELBM_EINVAL, "adjoint: step count %d outside 1..%d", n, A.nmax);
+  if (objective != ELBM_OBJ_DRAG && objective != ELBM_OBJ_KE) FAIL(c, ELBM_EINVAL, "unknown objective %d", objective);
+  if (objective == ELBM_OBJ_DRAG) {
+    if (body_level < 0 || body_level >= c->L) FAIL(c, ELBM_EINVAL, "bad body level %d", body_level);
+    if (!dir) FAIL(c, ELBM_EINVAL, "drag objective needs a direction");
+  }
+  A.pending = false;
+  A.n = n;
+  A.objective = objective;
+  A.body_level = objective == ELBM_OBJ_DRAG ? body_level : -1;
+  for (int q = 0; q < 3; ++q) A.dir[q] = (objective == ELBM_OBJ_DRAG) ? dir[q] : 0.0;
+  const size_t tb = comp_bytes(c->storage);
+  for (int l = 0; l < c->L; ++l) LCK(c, launch_zero(A.ws + A.o_lF[l], (size_t)c->lev[l].nb * c->D * BN * tb, c->stream));
+  if (objective == ELBM_OBJ_DRAG) {
+    LCK(c, launch_zero(c->ws + c->lev[body_level].o_drag, (size_t)c->lev[body_level].nb * 3 * 8, c->stream));
+    c->drag_steps[body_level] = 0;
+  }
+  hipEvent_t e0, e1;
+  HIPCK(c, hipEventCreate(&e0));
+  HIPCK(c, hipEventCreate(&e1));
+  HIPCK(c, hipEventRecord(e0, c->stream));
+  const int S = (n + A.K - 1) / A.K;
+  for (int s = 0; s < S; ++s) {
+    for (int l = 0; l < c->L; ++l) LCK(c, launch_copy(adj_ckpt(c, s, l), cur_state(c, l), level_state_bytes(c, l), c->stream));
+    elbm_status st = elbm_advance(c, std::min(A.K, n - s * A.K));
+    if (st) return st;
+  }
+  HIPCK(c, hipEventRecord(e1, c->stream));
+  double val = 0;
+  if (objective == ELBM_OBJ_DRAG) {
+    double F[3];
+    int64_t steps = 0;
+    elbm_status st = elbm_drag(c, body_level, F, &steps, 1);
+    if (st) return st;
+    val = (F[0] * dir[0] + F[1] * dir[1] + F[2] * dir[2]) / (double)(steps > 0 ? steps : 1);
+    for (int l = 0; l < c->L; ++l)
+      LCK(c, launch_zero(A.ws + A.o_lam[l][0], (size_t)c->lev[l].nb * c->Q * BN * tb, c->stream));
+  } else {
+    AdjKEArgs k;
+    memset(&k, 0, sizeof(k));
+    k.items = (const WorkItem *)(c->ws + c->o_redit);
+    k.n_items = (int)c->red_items.size();
+    k.lev = (const LevelStatic *)(c->ws + c->o_levstatic);
+    for (int l = 0; l < c->L; ++l) {
+      k.pop[l] = cur_state(c, l);
+      k.lam[l] = A.ws + A.o_lam[l][0];
+      k.lF[l] = A.ws + A.o_lF[l];
+    }
+    k.partials = (double *)(A.ws + A.o_part);
+    LCK(c, launch_adj_ke(c->D, c->storage, k, (double *)(A.ws + A.o_res), c->stream));
+    HIPCK(c, hipMemcpyAsync(&val, A.ws + A.o_res, 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  float ms = 0;
+  HIPCK(c, hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  A.ms[0] = ms;
+  for (int l = 0; l < c->L; ++l) A.cur[l] = 0;
+  A.J = val;
+  if (J) *J = val;
+  A.pending = true;
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_backward(elbm_ctx *c) {
+  if (!c) return ELBM_EINVAL;
+  auto &A = c->adj;
+  if (!A.bound || !A.pending) FAIL(c, ELBM_ESTATE, "adjoint_backward without a preceding adjoint_forward");
+  const int T = 1 << (c->L - 1);
+  const int S = (A.n + A.K - 1) / A.K;
+  std::vector<hipEvent_t> ev((size_t)3 * S);
+  for (auto &e : ev) HIPCK(c, hipEventCreate(&e));
+  elbm_status st = ELBM_OK;
+  for (int s = S - 1; s >= 0 && !st; --s) {
+    const int Ks = std::min(A.K, A.n - s * A.K);
+    for (int l = 0; l < c->L; ++l) LCK(c, launch_copy(adj_tape(c, l, 0), adj_ckpt(c, s, l), level_state_bytes(c, l), c->stream));
+    HIPCK(c, hipEventRecord(ev[(size_t)3 * s], c->stream));
+    for (int k = 1; k <= Ks && !st; ++k)
+      for (int t = 1; t <= T && !st; ++t) {
+        void *src[MAXL] = {}, *dst[MAXL] = {};
+        for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) {
+          const size_t slot = ((size_t)(k - 1) << l) + (size_t)((t >> (c->L - 1 - l)) - 1);
+          src[l] = adj_tape(c, l, slot);
+          dst[l] = adj_tape(c, l, slot + 1);
+        }
+        st = enqueue_tick_io(c, t, src, dst, c->stream, c->side, false, 0);
+      }
+    HIPCK(c, hipEventRecord(ev[(size_t)3 * s + 1], c->stream));
+    for (int k = Ks; k >= 1 && !st; --k)
+      for (int t = T; t >= 1 && !st; --t) st = adj_tick(c, k, t);
+    HIPCK(c, hipEventRecord(ev[(size_t)3 * s + 2], c->stream));
+  }
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  float rec = 0, rev = 0;
+  if (!st)
+    for (int s = 0; s < S; ++s) {
+      float a = 0, b = 0;
+      HIPCK(c, hipEventElapsedTime(&a, ev[(size_t)3 * s], ev[(size_t)3 * s + 1]));
+      HIPCK(c, hipEventElapsedTime(&b, ev[(size_t)3 * s + 1], ev[(size_t)3 * s + 2]));
+      rec += a;
+      rev += b;
+    }
+  for (auto &e : ev) hipEventDestroy(e);
+  if (st) return st;
+  A.ms[1] = rec;
+  A.ms[2] = rev;
+  A.pending = false;
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_read(elbm_ctx *c, int level, double *lam_dev, double *dJdF_dev) {
+  if (!c) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  auto &A = c->adj;
+  if (!A.bound || A.pending || A.n == 0) FAIL(c, ELBM_ESTATE, "adjoint_read before adjoint_backward");
+  const Level &L = c->lev[level];
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  if (lam_dev) LCK(c, launch_zero(lam_dev, tot * c->Q * 8, c->stream));
+  if (dJdF_dev) LCK(c, launch_zero(dJdF_dev, tot * c->D * 8, c->stream));
+  LCK(c, launch_adj_read(c->D, c->storage, A.ws + A.o_lam[level][A.cur[level]], A.ws + A.o_lF[level],
+                         (const LevelStatic *)(c->ws + c->o_levstatic), level, L.nb,
+                         (const int32_t *)(c->ws + L.o_borg), box, lam_dev, dJdF_dev, c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_velocity(elbm_ctx *c, int level, const double *rho, const double *u, const double *noise,
+                                  double *out) {
+  if (!c || !rho || !u || !out) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  auto &A = c->adj;
+  if (!A.bound || A.pending || A.n == 0) FAIL(c, ELBM_ESTATE, "adjoint_velocity before adjoint_backward");
+  const Level &L = c->lev[level];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  const size_t nd = tot * (1 + 2 * c->D + (noise ? c->Q : 0));
+  double *d = nullptr;
+  HIPCK(c, hipMalloc((void **)&d, nd * sizeof(double)));
+  double *dr = d, *du = d + tot, *dout = d + tot * (1 + c->D), *dn = noise ? d + tot * (1 + 2 * c->D) : nullptr;
+  hipError_t e = hipMemcpy(dr, rho, tot * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(du, u, tot * c->D * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && noise) e = hipMemcpy(dn, noise, tot * c->Q * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    FAIL(c, ELBM_EDEVICE, "upload: %s", hipGetErrorString(e));
+  }
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  int rc = launch_zero(dout, tot * c->D * 8, c->stream);
+  if (!rc)
+    rc = launch_adj_velocity(c->D, c->storage, A.ws + A.o_lam[level][A.cur[level]],
+                             (const LevelStatic *)(c->ws + c->o_levstatic), level, L.nb,
+                             (const int32_t *)(c->ws + L.o_borg), box, dr, du, dn, dout, c->stream);
+  if (!rc) rc = (int)hipStreamSynchronize(c->stream);
+  if (!rc) rc = (int)hipMemcpy(out, dout, tot * c->D * 8, hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (rc) FAIL(c, ELBM_EDEVICE, "adjoint_velocity: %s", hipGetErrorString((hipError_t)rc));
+  return ELBM_OK;
+}
+
+elbm_status elbm_adjoint_timing(const elbm_ctx *c, double ms[3]) {
+  if (!c || !ms) return ELBM_EINVAL;
+  for (int q = 0; q < 3; ++q) ms[q] = c->adj.ms[q];
   return ELBM_OK;
 }
 

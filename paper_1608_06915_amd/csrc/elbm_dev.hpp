@@ -91,10 +91,15 @@ struct PairStatic {
   int32_t pad;
 };
 
+// launch flags of the forward kernels
+enum { FL_DRAG = 1, FL_GAMMA = 2 };
+
 struct SCArgs {
   const WorkItem *items;
   int32_t n_items;
   int32_t remap;  // XCD-aware item mapping
+  int32_t flags;  // FL_DRAG: accumulate momentum exchange, FL_GAMMA: write gamma
+  int32_t pad;
   const LevelStatic *lev;
   void *src[MAXL];
   void *dst[MAXL];
@@ -125,6 +130,66 @@ struct CoupleArgs {
   const PairStatic *pairs;
   void *src[MAXL];
   void *dst[MAXL];
+  int32_t flags;  // FL_GAMMA: write gamma
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- discrete adjoint
+// Buffers of the reverse sweep, per level, in the compute type T (float, or double
+// for FP64 storage), brick layout as the populations:
+//   lam  adjoint of a post-collision state            [brick][Q][BN]
+//   lg   adjoint of the post-stream state of a tick    [brick+1][Q][BN], the extra
+//        brick stays zero and stands in for missing neighbours
+//   lF   gradient wrt the per-node force field         [brick][D][BN]
+struct AdjLevel {
+  const uint32_t *amask;  // [brick][BN]: populations that an outflow node downstream copies
+  int32_t zero_brick;     // index of the zero brick of lg
+  int32_t pad;
+};
+
+struct AdjArgs {  // collision adjoint and streaming transpose over whole bricks
+  const WorkItem *items;  // every brick of the arriving levels, thr of the tick
+  int32_t n_items;
+  int32_t drag_level;   // level whose momentum exchange is differentiated, or -1
+  double drag_seed[3];  // direction / number of substeps of the average
+  const LevelStatic *lev;
+  const AdjLevel *alev;
+  void *src[MAXL];  // forward state the tick read (storage type)
+  void *lam[MAXL];  // adjoint of the tick's output (collision) / of its input (transpose)
+  void *lg[MAXL];
+  void *lF[MAXL];
+};
+
+struct AdjCoupleArgs {
+  CoupleArgs c;     // tiles, items, ring, stencils, recomputed staged rows, src
+  void *lam[MAXL];
+  void *lg[MAXL];
+  void *lF[MAXL];
+  void *astage;     // [fine item][stage width]: adjoint of (rho~ - 1, u~, n~)
+};
+
+struct AdjPointArgs {
+  const GPoint *pts;
+  int32_t n;
+  int32_t pad;
+  const int32_t *tofs;            // per staged row: first transposed stencil entry (+1 sentinel)
+  const StencilEntry *tsten;      // slot = fine item, w = weight
+  const void *astage;
+  const LevelStatic *lev;
+  const PairStatic *pairs;
+  void *src[MAXL];
+  void *lg[MAXL];
+};
+
+struct AdjKEArgs {  // final kinetic energy: value, seed of lam, force-field seed
+  const WorkItem *items;  // every brick of every level
+  int32_t n_items;
+  int32_t pad;
+  const LevelStatic *lev;
+  void *pop[MAXL];
+  void *lam[MAXL];
+  void *lF[MAXL];
+  double *partials;  // [item][5], first entry used
 };
 
 // host-side launchers (kernels.hip)
@@ -153,6 +218,16 @@ int launch_force_scatter(int D, float *force, const double *F, int nbricks, cons
 int stage_row_width(int D);
 int couple_max_rows(int D, int st);
 int launch_zero(void *p, size_t bytes, void *stream);
+int launch_adj_collide(int D, int st, const AdjArgs &a, void *stream);
+int launch_adj_couple(int D, int st, const AdjCoupleArgs &a, void *stream);
+int launch_adj_points(int D, int st, const AdjPointArgs &a, void *stream);
+int launch_adj_transpose(int D, int st, const AdjArgs &a, void *stream);
+int launch_adj_ke(int D, int st, const AdjKEArgs &a, double *result, void *stream);
+int launch_adj_read(int D, int st, const void *lam, const void *lF, const LevelStatic *lev_dev, int level,
+                    int nbricks, const int32_t *borg, Dims box, double *lam_out, double *lF_out, void *stream);
+int launch_adj_velocity(int D, int st, const void *lam, const LevelStatic *lev_dev, int level, int nbricks,
+                        const int32_t *borg, Dims box, const double *rho, const double *u, const double *noise,
+                        double *out, void *stream);
 int launch_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 }  // namespace elbm

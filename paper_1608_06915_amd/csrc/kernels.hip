@@ -74,8 +74,8 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
       const T g = kbc_collide<D, T>(h, beta, F, hf, [&](int i, T v) {
         C::st((S *)(dstb + (uint32_t)((i * BN + n) * (int)sizeof(S))), v, T(wgt<D>(i)));
       });
-      if (L.gamma) L.gamma[(size_t)w.brick * BN + n] = (float)g;
-      if (cls & CLS_DRAG) {
+      if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)w.brick * BN + n] = (float)g;
+      if ((cls & CLS_DRAG) && (a.flags & FL_DRAG)) {
         // population i leaves towards x + c_i; that node is solid when population Q-1-i
         // bounced back: momentum exchange 2 c_i f'_i, from the values just stored
         for (int i = 0; i < Q; ++i) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
         }
       }
     }
-    if (wdrag) {  // deterministic block reduction of the momentum exchange
+    if (wdrag && (a.flags & FL_DRAG)) {  // deterministic block reduction of the momentum exchange
       double v[3] = {fd[0], fd[1], fd[2]};
 #pragma unroll
       for (int k = 0; k < 3; ++k)
@@ -171,7 +171,7 @@ template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &
   const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
   S *o = (S *)a.dst[c.level] + (size_t)c.brick * Q * BN + c.node;
   const T g = kbc_collide<D, T>(h, T(L.beta), F, hf, [&](int i, T v) { C::st(o + i * BN, v, T(wgt<D>(i))); });
-  if (L.gamma) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
+  if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
 }
 
 template <int D, int ST> __global__ __launch_bounds__(64) void k_couple(CoupleArgs a) {

@@ -31,7 +31,11 @@ EXPORTS = [
     "elbm_read_moments", "elbm_read_populations", "elbm_sample_populations", "elbm_reduce", "elbm_check",
     "elbm_drag", "elbm_set_gamma_output", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
     "elbm_state_bytes", "elbm_save_state", "elbm_load_state", "elbm_get_launch",
+    "elbm_adjoint_bytes", "elbm_adjoint_bind", "elbm_adjoint_forward", "elbm_adjoint_backward",
+    "elbm_adjoint_read", "elbm_adjoint_velocity", "elbm_adjoint_timing",
 ]
+
+OBJECTIVES = {"drag": 0, "ke": 1}
 
 
 class ElbmError(RuntimeError):
@@ -89,6 +93,13 @@ def lib():
             "elbm_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
             "elbm_save_state": [P, P],
             "elbm_load_state": [P, P],
+            "elbm_adjoint_bytes": [P, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+            "elbm_adjoint_bind": [P, P, ctypes.c_size_t, i32, i32],
+            "elbm_adjoint_forward": [P, i32, i32, i32, dp, dp],
+            "elbm_adjoint_backward": [P],
+            "elbm_adjoint_read": [P, i32, P, P],
+            "elbm_adjoint_velocity": [P, i32, dp, dp, dp, dp],
+            "elbm_adjoint_timing": [P, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -322,3 +333,94 @@ class Lattice:
     def load_state(self, src: torch.Tensor):
         assert src.is_cuda and src.numel() * src.element_size() >= self.state_bytes()
         self._ck(lib().elbm_load_state(self._h, ctypes.c_void_p(src.data_ptr())))
+
+    # -- discrete adjoint
+    def adjoint_bind(self, n_max: int, K: int):
+        """Allocate and bind the adjoint workspace for runs of up to n_max coarse steps,
+        checkpointing every K."""
+        n = ctypes.c_size_t()
+        self._ck(lib().elbm_adjoint_bytes(self._h, int(n_max), int(K), ctypes.byref(n)))
+        self.adjoint_workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.workspace.device)
+        ptr = self.adjoint_workspace.data_ptr()
+        self._ck(lib().elbm_adjoint_bind(self._h, ctypes.c_void_p(ptr + (-ptr) % 256), n.value, int(n_max), int(K)))
+
+    def adjoint_forward(self, n: int, objective="drag", body_level=0, direction=(1.0, 0.0, 0.0)) -> float:
+        J = ctypes.c_double()
+        d = _f3(direction)
+        self._ck(lib().elbm_adjoint_forward(self._h, int(n), OBJECTIVES[objective], int(body_level), _dp(d),
+                                            ctypes.byref(J)))
+        return J.value
+
+    def adjoint_backward(self):
+        self._ck(lib().elbm_adjoint_backward(self._h))
+
+    def adjoint_read(self, level):
+        """(dJ/df0 [Q, *box], dJ/dF [D, *box]) as float64 device tensors."""
+        sh = self.shape(level)
+        dev = self.workspace.device
+        lam = torch.empty((self.Q,) + sh, dtype=torch.float64, device=dev)
+        gF = torch.empty((self.D,) + sh, dtype=torch.float64, device=dev)
+        self._ck(lib().elbm_adjoint_read(self._h, level, ctypes.c_void_p(lam.data_ptr()),
+                                         ctypes.c_void_p(gF.data_ptr())))
+        self.synchronize()
+        return lam, gF
+
+    def adjoint_velocity(self, level, rho, u, noise=None):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+        out = np.zeros_like(u)
+        self._ck(lib().elbm_adjoint_velocity(self._h, level, _dp(rho), _dp(u), None if nz is None else _dp(nz),
+                                             _dp(out)))
+        return out
+
+    def adjoint_timing(self):
+        ms = np.zeros(3)
+        self._ck(lib().elbm_adjoint_timing(self._h, _dp(ms)))
+        return tuple(ms)
+
+
+class ForceObjective(torch.autograd.Function):
+    """J(F_0, ..., F_{L-1}) for per-level force fields F_l ([D, *box] float64 device
+    tensors): loads the initial state, sets the fields, runs n coarse steps through
+    elbm_adjoint_forward; backward runs elbm_adjoint_backward and returns dJ/dF_l."""
+
+    @staticmethod
+    def forward(ctx, lat, state, n, objective, body_level, direction, *forces):
+        lat.load_state(state)
+        for l, F in enumerate(forces):
+            lat.set_force_field(l, F.detach().contiguous())
+        J = lat.adjoint_forward(n, objective, body_level, direction)
+        ctx.lat, ctx.nf = lat, len(forces)
+        return torch.tensor(J, dtype=torch.float64, device=state.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        ctx.lat.adjoint_backward()
+        grads = tuple(gJ * ctx.lat.adjoint_read(l)[1] for l in range(ctx.nf))
+        return (None,) * 6 + grads
+
+
+class VelocityObjective(torch.autograd.Function):
+    """J(u0_0, ..., u0_{L-1}) for per-level initial velocity fields ([D, *box] float64
+    tensors, initialised with rho0 and noise as elbm_init_fields); backward returns
+    dJ/du0_l through elbm_adjoint_velocity."""
+
+    @staticmethod
+    def forward(ctx, lat, rho, noise, n, objective, body_level, direction, *u0):
+        host = [u.detach().cpu().numpy() for u in u0]
+        for l, u in enumerate(host):
+            lat.init(l, rho[l], u, None if noise is None else noise[l])
+        J = lat.adjoint_forward(n, objective, body_level, direction)
+        ctx.lat, ctx.rho, ctx.noise, ctx.u0 = lat, rho, noise, host
+        ctx.dev = [u.device for u in u0]
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        ctx.lat.adjoint_backward()
+        grads = []
+        for l, u in enumerate(ctx.u0):
+            g = ctx.lat.adjoint_velocity(l, ctx.rho[l], u, None if ctx.noise is None else ctx.noise[l])
+            grads.append(gJ.to(torch.float64).cpu() * torch.from_numpy(g).to(ctx.dev[l]))
+        return (None,) * 7 + tuple(grads)
