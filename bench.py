@@ -9,8 +9,9 @@ gather/reconstruction/coalescence, every collision), replayed as one HIP graph.
 Metric: fine-equivalent MLUPS = sum_l N_l 2^l x coarse steps / s / 1e6 (N_l: fluid
 nodes of level l), i.e. the paper's time-step-weighted "equivalent fine level
 points" per second.  Also reported: the same for weight-shifted FP16 storage, the
-dominant kernel's roofline (stream-collide, HBM bound) and the FP64 CPU oracle on
-the same workload.
+dominant kernel's roofline (stream-collide, HBM bound), the adjoint/forward time
+ratio (default: two-level D2Q9 cylinder, mean drag over 2000 coarse steps,
+checkpoints every 100) and the FP64 CPU oracle on the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
 """
@@ -121,6 +122,58 @@ def run_gpu(sp, storage, steps, warmup, tune):
     return lat, ms, sc_ms, n_launch, tot_ms, ok
 
 
+def _init(lat, sp):
+    for l in range(sp.levels):
+        lo, n = lat.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        lat.init(l, rho, u, nz)
+
+
+def run_adjoint(name, storage, n, K):
+    """Forward time of n coarse steps vs a full adjoint run (forward with checkpoints
+    every K, recomputation, reverse sweep) of the mean drag on the body level, or of
+    the final kinetic energy when the workload has no body."""
+    import torch
+
+    from paper_1608_06915_amd import elbm, synth
+
+    sp, desc = workload(name)
+    lat = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    synth.apply(sp, lat)
+    lat.bind()
+    _init(lat, sp)
+    obj, bl = ("drag", sp.body_level) if sp.body_level is not None else ("ke", 0)
+    lat.adjoint_bind(n, K)
+    lat.adjoint_forward(min(n, K), obj, bl, (1.0, 0.0, 0.0))  # warm-up: graphs, code paths
+    lat.adjoint_backward()
+    _init(lat, sp)
+    lat.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.advance(n)
+    end.record(lat.stream)
+    end.synchronize()
+    fwd_ms = start.elapsed_time(end)
+    _init(lat, sp)
+    lat.synchronize()
+    t0 = time.time()
+    J = lat.adjoint_forward(n, obj, bl, (1.0, 0.0, 0.0))
+    lat.adjoint_backward()
+    wall_ms = (time.time() - t0) * 1e3
+    ms = lat.adjoint_timing()
+    fe = fine_equiv_updates(lat, sp)
+    adj_ms = sum(ms)
+    print("bench: adjoint %s %s n=%d K=%d forward %.1f ms, adjoint %.1f ms (fwd+ckpt %.1f, recompute %.1f, "
+          "reverse %.1f), ratio %.2f" % (name, storage, n, K, fwd_ms, adj_ms, ms[0], ms[1], ms[2], adj_ms / fwd_ms),
+          file=sys.stderr, flush=True)
+    return {"workload": desc, "storage": storage, "objective": obj, "coarse_steps": n, "checkpoint_every": K,
+            "forward_ms": round(fwd_ms, 3), "adjoint_ms": round(adj_ms, 3),
+            "adjoint_breakdown_ms": {"forward_with_checkpoints": round(ms[0], 3), "recompute": round(ms[1], 3),
+                                     "reverse": round(ms[2], 3)},
+            "ratio": round(adj_ms / fwd_ms, 3), "ratio_wall": round(wall_ms / fwd_ms, 3),
+            "forward_MLUPS_fe": round(fe * n / (fwd_ms / 1e3) / 1e6, 1), "J": J}
+
+
 def cpu_baseline(sp, fe_updates, steps):
     import oracle
 
@@ -150,7 +203,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
-    ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-workload", default="cylinder2d")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-K", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
@@ -164,7 +221,7 @@ def main():
     sp, desc = workload(args.workload)
     print("bench: workload=%s storage=%s steps=%d warmup=%d" % (args.workload, args.storage, args.steps,
                                                                 args.warmup), file=sys.stderr, flush=True)
-    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, args.tune)
+    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, not args.no_tune)
     fe = fine_equiv_updates(lat, sp)
     value = fe * args.steps / (ms / 1e3) / 1e6
     counts = mode_counts(lat, sp)
@@ -205,7 +262,7 @@ def main():
                      "bytes_per_node_update": 2 * sp.Q * sbytes},
     }
     if not args.no_half and args.storage == "f32":
-        lat2, ms2, sc2, nl2, _, ok2 = run_gpu(sp, "f16s", args.steps, args.warmup, args.tune)
+        lat2, ms2, sc2, nl2, _, ok2 = run_gpu(sp, "f16s", args.steps, args.warmup, not args.no_tune)
         v2 = fe * args.steps / (ms2 / 1e3) / 1e6
         b2, l2, _ = sc_bytes_per_coarse_step(sp, counts, 2)
         a2 = (b2 / l2) / (sc2 / max(nl2, 1) / 1e3) / 1e9
@@ -214,6 +271,8 @@ def main():
                        "stream_collide_GBs": round(a2, 1), "stable": ok2}
         print("bench: f16s %.1f MLUPS_fe" % v2, file=sys.stderr, flush=True)
         del lat2
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint(args.adjoint_workload, args.storage, args.adjoint_steps, args.adjoint_K)
     if not args.no_cpu:
         mlups, dt, setup = cpu_baseline(sp, fe, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(mlups, 4), "unit": "MLUPS (fine-equivalent)", "cores": 1,
