@@ -33,6 +33,34 @@ METRIC = "fine-equiv MLUPS & HBM % (FP32 vs FP16 store); adjoint/forward time ra
 STORE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lbm_device.hpp", "elbm_dev.hpp"):
+        with open(os.path.join(ROOT, "paper_1608_06915_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, storage):
+    """HBM bytes per stream-collide launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary of this workload, or None if there is none or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_stream_collide.%s.%s.hbm_counters.md" % (workload_name, storage))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def workload(name):
     from paper_1608_06915_amd import synth
 
@@ -208,7 +236,20 @@ def main():
     ap.add_argument("--adjoint-workload", default="cylinder2d")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n, "launches": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
         raise SystemExit(2)
@@ -256,7 +297,8 @@ def main():
         "hbm_pct_alg": round(hbm_pct, 2),
         "stable": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(args.workload, args.storage),
                      "kernel": "k_stream_collide", "bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
                      "bytes_per_node_update": 2 * sp.Q * sbytes},

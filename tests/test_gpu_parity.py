@@ -206,3 +206,48 @@ def test_deterministic_repeat(elbm):
         assert np.array_equal(a.get_f(l), b.get_f(l), equal_nan=True)
     ra, rb = a.reduce(), b.reduce()
     assert ra[0] == rb[0] and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2]
+
+
+# ----------------------------------------------------------------- full-size workloads
+# The oracle cannot run the full-size workloads for many steps (9-18 s per coarse
+# step).  After k coarse steps on the GPU, in the autotuned launch configuration the
+# benchmark times, the GPU state of every level is loaded into the oracle and both
+# advance one more coarse step; every population of every node is compared.
+@pytest.mark.parametrize("name,storage,k,bound", [
+    ("channel3d", "f32", 50, 1e-5),
+    ("channel3d", "f16s", 50, 1e-3),
+    ("sphere3d", "f32", 20, 1e-5),
+    ("forest3d", "f32", 20, 1e-5),
+    ("cylinder2d", "f32", 200, 1e-5),
+])
+def test_full_size_one_step_from_gpu_state(elbm, name, storage, k, bound):
+    import torch
+
+    sp = getattr(synth, name)()
+    print("full-size case %s storage=%s k=%d" % (name, storage, k), flush=True)
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    synth.apply(sp, g)
+    g.bind()
+    for l in range(sp.levels):
+        lo, n = g.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        g.init(l, rho, u, nz)
+    g.tune(None, steps=2)
+    g.advance(k)
+    assert g.check()
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
+    synth.apply(sp, o)
+    for l in range(sp.levels):
+        o.set_f(l, g.get_f(l))
+    g.advance(1)
+    g.synchronize()
+    o.advance(1)
+    e_u = max_du(g, o, sp)
+    e_f = max_df(g, o, sp)
+    mg, _, bad = g.reduce()
+    mo, _ = o.reduce()
+    print("%s %s: max|du|/U %.3e  max|df| %.3e  mass rel %.3e" % (name, storage, e_u, e_f, abs(mg - mo) / mo))
+    assert bad == 0
+    assert e_u < bound
+    del g
+    torch.cuda.empty_cache()
