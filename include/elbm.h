@@ -169,15 +169,19 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
  * for the persistent stream-collide grid (0: one workgroup per brick), XCD-aware
  * brick-to-workgroup mapping, threads per workgroup (64, 128 or 256; each thread
  * covers 256/threads nodes of its brick), register-budget variant of the
- * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD). */
+ * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD),
+ * pipeline (1: persistent software-pipelined stream-collide, wg_per_cu workgroups of
+ * 256 threads per CU, default 3; threads and occupancy are then ignored).  Every
+ * configuration gives bitwise identical populations. */
 elbm_status elbm_set_launch(elbm_ctx *ctx, int use_graph, int wg_per_cu, int xcd_remap, int threads,
-                            int occupancy);
-/* Current launch configuration: {use_graph, wg_per_cu, xcd_remap, threads, occupancy}. */
-elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[5]);
+                            int occupancy, int pipeline);
+/* Current launch configuration: {use_graph, wg_per_cu, xcd_remap, threads, occupancy,
+ * pipeline}. */
+elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[6]);
 /* Autotune the launch configuration by timing `steps` coarse steps per candidate;
- * results cached in cache_path (one "key": [graph, wg_per_cu, xcd, threads, occupancy]
- * line per workload shape; may be NULL).  The state is restored; drag accumulators
- * are reset. */
+ * results cached in cache_path (one "key": [graph, wg_per_cu, xcd, threads, occupancy,
+ * pipeline] line per workload shape; may be NULL).  The state is restored; drag
+ * accumulators are reset. */
 elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
 /* Time `steps` coarse steps with HIP events around every stream-collide launch;
  * returns the total and summed stream-collide milliseconds and launch count.

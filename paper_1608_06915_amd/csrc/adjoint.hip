@@ -305,12 +305,7 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_collide(Ad
   const int wthr = __builtin_amdgcn_readfirstlane((int)w.thr);
   const LevelStatic &L = a.lev[wl];
   const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
-  uint32_t off[27];
-  static_for<0, 27>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    const int nb = __builtin_amdgcn_readfirstlane(nbp[k]);
-    off[k] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-  });
+  cptr<int32_t> nbc = cst(L.nbr) + (size_t)w.brick * 27;
   auto boff = [&](int code) {
     const int nb = nbp[code];
     return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
@@ -337,8 +332,10 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_collide(Ad
       const Lane<D> ln(x, y, z);
       pull_special<D, ST>(srcb, boff, ln, n, cls, mask, L, h);
     } else {
+      uint32_t mid[9], side[9];
+      bulk_offsets<D, ST>([&](int q) { return (int)nbc[q]; }, z, mid, side);
       const BulkLane<D> bl(x, y, z);
-      pull_bulk<D, ST>(srcb, off, bl, h);
+      pull_bulk<D, ST>(buf_rsrc(srcb, (uint32_t)L.nbricks * brick_bytes<D, ST>()), mid, side, bl, h);
     }
     T l[Q];
 #pragma unroll

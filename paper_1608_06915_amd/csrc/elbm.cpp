@@ -124,7 +124,7 @@ struct elbm_ctx {
   int parity = 0;  // buffer index of level 0
   int64_t drag_steps[MAXL] = {};
   // launch config
-  int use_graph = 1, wg_per_cu = 0, xcd_remap = 1, threads = 256, occ = 1;
+  int use_graph = 1, wg_per_cu = 0, xcd_remap = 1, threads = 256, occ = 1, pipe = 0;
   bool gamma_on = false;
   bool timing = false;
   std::vector<hipEvent_t> tev;
@@ -629,17 +629,27 @@ elbm_status build_level_links(elbm_ctx *c, int l) {
       if (mode == 2) m2 = true;
       if (mode > 0 || L.ring[k] || L.pd[k] <= 1) L.n_update++;
     }
+    // plain bricks: every node fluid, stream-collided at this threshold, plain links only
+    bool plain1 = true, plain2 = true;
+    for (int n = 0; n < BN; ++n) {
+      const uint8_t cl = L.cls[(size_t)b * BN + n];
+      const bool ok = (cl & CLS_FLUID) && !(cl & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW | CLS_DRAG));
+      plain1 = plain1 && ok && (cl & CLS_MODE) >= 1;
+      plain2 = plain2 && ok && (cl & CLS_MODE) >= 2;
+    }
     WorkItem w;
     w.brick = b;
     w.level = (uint8_t)l;
     w.drag = dr;
-    w.pad = 0;
+    w.flags = 0;
     if (m1) {
       w.thr = 1;
+      w.flags = plain1 ? WI_PLAIN : 0;
       L.items1.push_back(w);
     }
     if (m2) {
       w.thr = 2;
+      w.flags = plain2 ? WI_PLAIN : 0;
       L.items2.push_back(w);
     }
     L.any_drag = L.any_drag || dr;
@@ -911,7 +921,7 @@ void build_schedule(elbm_ctx *c) {
       w.level = (uint8_t)l;
       w.thr = 0;
       w.drag = 0;
-      w.pad = 0;
+      w.flags = 0;
       c->red_items.push_back(w);
     }
 }
@@ -943,7 +953,7 @@ void build_layout(elbm_ctx *c) {
   }
   c->o_levstatic = take(sizeof(LevelStatic) * MAXL);
   c->o_pairstatic = take(sizeof(PairStatic) * MAXL);
-  c->o_sc = take(c->sc_all.size() * sizeof(WorkItem));
+  c->o_sc = take(c->sc_all.size() * sizeof(ItemRec));
   c->o_gp = take(c->gp_all.size() * sizeof(GPoint));
   c->o_fine = take(c->fine_all.size() * sizeof(CItem));
   c->o_ring = take(c->ring_all.size() * sizeof(CItem));
@@ -1060,7 +1070,7 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     LCK(c, launch_couple(c->D, c->storage, a, cs));
   }
   SCArgs s;
-  s.items = (const WorkItem *)(c->ws + c->o_sc) + tk.sc_off;
+  s.items = (const ItemRec *)(c->ws + c->o_sc) + tk.sc_off;
   s.n_items = (int)tk.sc_n;
   s.remap = c->xcd_remap;
   s.flags = flags;
@@ -1073,7 +1083,9 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
   LaunchCfg cfg;
   cfg.threads = c->threads;
   cfg.occ = c->occ;
+  cfg.pipe = c->pipe;
   cfg.grid = c->wg_per_cu > 0 ? std::min<int>((int)tk.sc_n, c->wg_per_cu * c->cu_count) : (int)tk.sc_n;
+  if (c->pipe) cfg.grid = std::min<int>((int)tk.sc_n, (c->wg_per_cu > 0 ? c->wg_per_cu : 3) * c->cu_count);
   if (c->timing) {
     hipEvent_t e0, e1;
     HIPCK(c, hipEventCreate(&e0));
@@ -1162,7 +1174,7 @@ void adj_build_tables(elbm_ctx *c) {
         w.level = (uint8_t)l;
         w.thr = (uint8_t)((l == lmin && l > 0) ? 1 : 2);
         w.drag = 0;
-        w.pad = 0;
+        w.flags = 0;
         A.items.push_back(w);
       }
     A.tick.push_back({off, A.items.size() - off});
@@ -1640,8 +1652,17 @@ elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
     HIPCK(c, hipMemset(c->ws + L.o_pop[1], 0, pb));
     c->drag_steps[l] = 0;
   }
-  if (!c->sc_all.empty())
-    HIPCK(c, hipMemcpy(c->ws + c->o_sc, c->sc_all.data(), c->sc_all.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  if (!c->sc_all.empty()) {
+    // stream-collide items carry their neighbour bricks (one scalar fetch per item)
+    std::vector<ItemRec> rec(c->sc_all.size());
+    for (size_t i = 0; i < rec.size(); ++i) {
+      memset(&rec[i], 0, sizeof(ItemRec));
+      rec[i].w = c->sc_all[i];
+      const Level &L = c->lev[c->sc_all[i].level];
+      for (int k = 0; k < 27; ++k) rec[i].nbr[k] = L.nbr[(size_t)c->sc_all[i].brick * 27 + k];
+    }
+    HIPCK(c, hipMemcpy(c->ws + c->o_sc, rec.data(), rec.size() * sizeof(ItemRec), hipMemcpyHostToDevice));
+  }
   if (!c->gp_all.empty())
     HIPCK(c, hipMemcpy(c->ws + c->o_gp, c->gp_all.data(), c->gp_all.size() * sizeof(GPoint), hipMemcpyHostToDevice));
   if (!c->fine_all.empty())
@@ -1875,7 +1896,8 @@ elbm_status elbm_set_gamma_output(elbm_ctx *c, int enable) {
   return ELBM_OK;
 }
 
-elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_remap, int threads, int occupancy) {
+elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_remap, int threads, int occupancy,
+                            int pipeline) {
   if (!c) return ELBM_EINVAL;
   if (occupancy != 1 && occupancy != 4) FAIL(c, ELBM_EINVAL, "occupancy variant must be 1 or 4");
   if (threads != 64 && threads != 128 && threads != 256) FAIL(c, ELBM_EINVAL, "threads must be 64, 128 or 256");
@@ -1885,17 +1907,19 @@ elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_r
   c->xcd_remap = xcd_remap != 0;
   c->threads = threads;
   c->occ = occupancy;
+  c->pipe = pipeline != 0;
   invalidate_graphs(c);
   return ELBM_OK;
 }
 
-elbm_status elbm_get_launch(const elbm_ctx *c, int32_t cfg[5]) {
+elbm_status elbm_get_launch(const elbm_ctx *c, int32_t cfg[6]) {
   if (!c || !cfg) return ELBM_EINVAL;
   cfg[0] = c->use_graph;
   cfg[1] = c->wg_per_cu;
   cfg[2] = c->xcd_remap;
   cfg[3] = c->threads;
   cfg[4] = c->occ;
+  cfg[5] = c->pipe;
   return ELBM_OK;
 }
 
@@ -1987,10 +2011,10 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
       char line[512];
       while (fgets(line, sizeof(line), f)) {
         char k[256];
-        int g, w, x, t, o;
-        if (sscanf(line, " \"%255[^\"]\": [%d, %d, %d, %d, %d]", k, &g, &w, &x, &t, &o) == 6 && key == k) {
+        int g, w, x, t, o, p;
+        if (sscanf(line, " \"%255[^\"]\": [%d, %d, %d, %d, %d, %d]", k, &g, &w, &x, &t, &o, &p) == 7 && key == k) {
           fclose(f);
-          return elbm_set_launch(c, g, w, x, t, o);
+          return elbm_set_launch(c, g, w, x, t, o, p);
         }
       }
       fclose(f);
@@ -2003,19 +2027,21 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
   elbm_status s = elbm_save_state(c, save);
   const int par0 = c->parity;
   struct Cand {
-    int w, x, t, o;
+    int w, x, t, o, p;
   };
   std::vector<Cand> cands;
   for (int o : {1, 4})
     for (int w : {0, 2, 4, 8})
       for (int x : {0, 1})
-        for (int t : {256, 128}) cands.push_back({w, x, t, o});
+        for (int t : {256, 128}) cands.push_back({w, x, t, o, 0});
+  for (int w : {2, 3, 4})
+    for (int x : {0, 1}) cands.push_back({w, x, 256, 1, 1});
   double best = 1e30;
-  Cand bc = {0, 1, 256, 1};
+  Cand bc = {0, 1, 256, 1, 0};
   hipEvent_t a = nullptr, b = nullptr;
   if (!s && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
     for (const Cand &cd : cands) {
-      if ((s = elbm_set_launch(c, 1, cd.w, cd.x, cd.t, cd.o))) break;
+      if ((s = elbm_set_launch(c, 1, cd.w, cd.x, cd.t, cd.o, cd.p))) break;
       if ((s = elbm_advance(c, 1))) break;  // warm-up and graph build
       hipEventRecord(a, c->stream);
       if ((s = elbm_advance(c, steps))) break;
@@ -2037,7 +2063,7 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
   hipStreamSynchronize(c->stream);
   hipFree(save);
   if (s) return s;
-  s = elbm_set_launch(c, 1, bc.w, bc.x, bc.t, bc.o);
+  s = elbm_set_launch(c, 1, bc.w, bc.x, bc.t, bc.o, bc.p);
   if (s) return s;
   for (int l = 0; l < c->L; ++l) {  // the timing runs advanced the drag accumulators
     LCK(c, launch_zero(c->ws + c->lev[l].o_drag, (size_t)c->lev[l].nb * 3 * 8, c->stream));
@@ -2046,7 +2072,7 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
   if (cache_path) {
     FILE *f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "\"%s\": [%d, %d, %d, %d, %d]\n", key.c_str(), 1, bc.w, bc.x, bc.t, bc.o);
+      fprintf(f, "\"%s\": [%d, %d, %d, %d, %d, %d]\n", key.c_str(), 1, bc.w, bc.x, bc.t, bc.o, bc.p);
       fclose(f);
     }
   }

@@ -38,8 +38,17 @@ struct WorkItem {  // one brick of one level in a stream-collide launch
   uint8_t level;
   uint8_t thr;    // process nodes with mode >= thr
   uint8_t drag;   // brick holds drag nodes
-  uint8_t pad;
+  uint8_t flags;  // WI_PLAIN: every node is fluid, has mode >= thr and only plain links
 };
+enum : uint8_t { WI_PLAIN = 1 };
+static_assert(sizeof(WorkItem) == 8, "kernels read a WorkItem as one little-endian 64-bit word");
+
+struct ItemRec {  // stream-collide work item with its 27 neighbour bricks (one scalar fetch)
+  WorkItem w;
+  int32_t nbr[27];  // neighbour brick per displacement code, -1 if absent
+  int32_t pad[3];
+};
+static_assert(sizeof(ItemRec) == 128, "ItemRec layout");
 
 struct GPoint {  // coarse-aligned interpolation point of an interface (gather phase)
   int32_t brick;
@@ -95,7 +104,7 @@ struct PairStatic {
 enum { FL_DRAG = 1, FL_GAMMA = 2 };
 
 struct SCArgs {
-  const WorkItem *items;
+  const ItemRec *items;
   int32_t n_items;
   int32_t remap;  // XCD-aware item mapping
   int32_t flags;  // FL_DRAG: accumulate momentum exchange, FL_GAMMA: write gamma
@@ -196,7 +205,8 @@ struct AdjKEArgs {  // final kinetic energy: value, seed of lam, force-field see
 struct LaunchCfg {
   int grid;
   int threads;
-  int occ;  // stream-collide register-budget variant: 1 uncapped, 4 capped at 128 VGPRs
+  int occ;   // stream-collide register-budget variant: 1 uncapped, 4 capped at 128 VGPRs
+  int pipe;  // 1: persistent software-pipelined stream-collide (grid = wg_per_cu x CUs)
 };
 int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *stream);
 int launch_gather(int D, int st, const GatherArgs &a, void *stream);

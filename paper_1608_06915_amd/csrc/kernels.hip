@@ -30,64 +30,125 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   for (int base = 0; base < a.n_items; base += G) {
     const int idx = base + me;
     if (idx >= a.n_items) break;
-    WorkItem w = a.items[idx];
-    // the item is the same for the whole workgroup: keep it in scalar registers
-    w.brick = __builtin_amdgcn_readfirstlane(w.brick);
-    const int wl = __builtin_amdgcn_readfirstlane((int)w.level);
-    const int wthr = __builtin_amdgcn_readfirstlane((int)w.thr);
-    const int wdrag = __builtin_amdgcn_readfirstlane((int)w.drag);
-    const LevelStatic &L = a.lev[wl];
-    const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
-    uint32_t off[27];
-    static_for<0, 27>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      const int nb = __builtin_amdgcn_readfirstlane(nbp[k]);
-      off[k] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-    });
+    // the item, its level's constants and its neighbour bricks are wave-uniform:
+    // scalar loads, issued together, with no dependent vector round trip
+    cptr<ItemRec> rec = cst(a.items) + idx;
+    const uint64_t wi = *(cptr<uint64_t>)rec;  // the WorkItem as one 8-byte word
+    WorkItem w;
+    w.brick = (int32_t)(uint32_t)wi;
+    const int wl = (int)((wi >> 32) & 0xff), wthr = (int)((wi >> 40) & 0xff), wdrag = (int)((wi >> 48) & 0xff);
+    const bool plain = ((wi >> 56) & WI_PLAIN) != 0;
+    cptr<LevelStatic> Lc = cst(a.lev) + wl;
+    cptr<int32_t> nbp = rec->nbr;
+    const uint8_t *__restrict__ cls_p = Lc->cls + (size_t)w.brick * BN;
+    const float *__restrict__ force_p = Lc->force;
+    float *__restrict__ gamma_p = (a.flags & FL_GAMMA) ? Lc->gamma : nullptr;
+    const T Fu[3] = {T(Lc->F[0]), T(Lc->F[1]), T(Lc->F[2])};
+    const T fsc = T(Lc->fscale);
     const char *__restrict__ srcb = (const char *)a.src[wl];
-    char *__restrict__ dstb = (char *)a.dst[wl] + (size_t)w.brick * brick_bytes<D, ST>();
-    const T beta = T(L.beta);
+    const uint32_t lbytes = (uint32_t)Lc->nbricks * brick_bytes<D, ST>();
+    const Rsrc rsrc = buf_rsrc(a.src[wl], lbytes), rdst = buf_rsrc(a.dst[wl], lbytes);
+    const uint32_t dbrick = (uint32_t)w.brick * brick_bytes<D, ST>();
+    const T beta = T(Lc->beta);
     double fd[3] = {0, 0, 0};
-    auto boff = [&](int code) {
-      const int nb = nbp[code];
-      return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-    };
+    __shared__ uint32_t s_nbo[27];  // neighbour-brick byte offsets for per-lane lookups
+    if (!plain) {
+      if (threadIdx.x < 27) {
+        const int nb = nbp[threadIdx.x];
+        s_nbo[threadIdx.x] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+      }
+      __syncthreads();
+    }
+    if (plain && blockDim.x == BN / 2) {
+      // plain brick, two nodes per thread: both nodes' loads are issued before either
+      // collision, doubling the bytes in flight per wavefront
+      const int n0 = threadIdx.x, n1 = n0 + BN / 2;
+      int x0, y0, z0, x1, y1, z1;
+      node_xyz<D>(n0, x0, y0, z0);
+      node_xyz<D>(n1, x1, y1, z1);
+      if (D == 3) {
+        z0 = __builtin_amdgcn_readfirstlane(z0);
+        z1 = __builtin_amdgcn_readfirstlane(z1);
+      }
+      uint32_t mid[9], side0[9], side1[9];
+      bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z0, mid, side0);
+      bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z1, mid, side1);
+      T h0[Q], h1[Q];
+      pull_bulk<D, ST>(rsrc, mid, side0, BulkLane<D>(x0, y0, z0), h0);
+      pull_bulk<D, ST>(rsrc, mid, side1, BulkLane<D>(x1, y1, z1), h1);
+      auto one = [&](T (&h)[Q], int n) {
+        T F[3] = {Fu[0], Fu[1], Fu[2]};
+        if (force_p) {
+          const float *fp = force_p + (size_t)w.brick * D * BN + n;
+#pragma unroll
+          for (int c = 0; c < D; ++c) F[c] += T(fp[c * BN]) * fsc;
+        }
+        const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
+        const T g = kbc_collide<D, T>(h, beta, F, hf, [&](int i, T v) {
+          C::stb(rdst, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)), v, T(wgt<D>(i)));
+        });
+        if (gamma_p) gamma_p[(size_t)w.brick * BN + n] = (float)g;
+      };
+      one(h0, n0);
+      one(h1, n1);
+      continue;
+    }
     for (int n = threadIdx.x; n < BN; n += blockDim.x) {
-      const uint8_t cls = L.cls[(size_t)w.brick * BN + n];
-      if ((cls & CLS_MODE) < wthr) continue;
+      uint8_t cls = CLS_FLUID | 2;
+      if (!plain) {
+        cls = cls_p[n];
+        if ((cls & CLS_MODE) < wthr) continue;
+      }
       int x, y, z;
       node_xyz<D>(n, x, y, z);
       if (D == 3) z = __builtin_amdgcn_readfirstlane(z);  // one z-slice per wavefront
       T h[Q];
       uint32_t mask = 0;
-      if (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) {
-        mask = L.mask[(size_t)w.brick * BN + n];
-        const Lane<D> ln(x, y, z);
-        pull_special<D, ST>(srcb, boff, ln, n, cls, mask, L, h);
-      } else {
+      if (!plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW))) {
+        mask = Lc->mask[(size_t)w.brick * BN + n];
+        uint32_t mid[9], side[9];
+        bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z, mid, side);
         const BulkLane<D> bl(x, y, z);
-        pull_bulk<D, ST>(srcb, off, bl, h);
+        pull_links<D, ST>(rsrc, mid, side, bl, [&](int q) { return s_nbo[q]; }, dbrick, x, y, z, n, cls, mask, Lc, h);
+      } else {
+        uint32_t mid[9], side[9];
+        bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z, mid, side);
+        const BulkLane<D> bl(x, y, z);
+        pull_bulk<D, ST>(rsrc, mid, side, bl, h);
       }
-      T F[3];
-      node_force<D, T>(L, w.brick, n, F);
+      T F[3] = {Fu[0], Fu[1], Fu[2]};
+      if (force_p) {
+        const float *fp = force_p + (size_t)w.brick * D * BN + n;
+#pragma unroll
+        for (int c = 0; c < D; ++c) F[c] += T(fp[c * BN]) * fsc;
+      }
       const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
       const T g = kbc_collide<D, T>(h, beta, F, hf, [&](int i, T v) {
-        C::st((S *)(dstb + (uint32_t)((i * BN + n) * (int)sizeof(S))), v, T(wgt<D>(i)));
+        C::stb(rdst, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)), v, T(wgt<D>(i)));
       });
-      if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)w.brick * BN + n] = (float)g;
-      if ((cls & CLS_DRAG) && (a.flags & FL_DRAG)) {
+      if (gamma_p) gamma_p[(size_t)w.brick * BN + n] = (float)g;
+      if (!plain && (cls & CLS_DRAG) && (a.flags & FL_DRAG)) {
         // population i leaves towards x + c_i; that node is solid when population Q-1-i
-        // bounced back: momentum exchange 2 c_i f'_i, from the values just stored
-        for (int i = 0; i < Q; ++i) {
-          if (!((mask >> (Q - 1 - i)) & 1u)) continue;
-          const double fi =
-              wgt<D>(i) + (double)C::ld((const S *)(dstb + (uint32_t)((i * BN + n) * (int)sizeof(S))), T(wgt<D>(i)));
-          fd[0] += 2.0 * (double)cxo(i) * fi;
-          fd[1] += 2.0 * (double)cyo(i) * fi;
-          fd[2] += 2.0 * (double)czo<D>(i) * fi;
-        }
+        // bounced back: momentum exchange 2 c_i f'_i, from the values just stored (all
+        // read back at once, then accumulated under the link mask)
+        T r[Q];
+        static_for<0, Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          r[i] = C::ldb(rdst, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)),
+                        T(wgt<D>(i)));
+        });
+        static_for<0, Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if ((mask >> (Q - 1 - i)) & 1u) {
+            const double fi = wgt<D>(i) + (double)r[i];
+            fd[0] += 2.0 * (double)cxo(i) * fi;
+            fd[1] += 2.0 * (double)cyo(i) * fi;
+            fd[2] += 2.0 * (double)czo<D>(i) * fi;
+          }
+        });
       }
     }
+    if (!plain) __syncthreads();  // s_nbo is rewritten by the next item
     if (wdrag && (a.flags & FL_DRAG)) {  // deterministic block reduction of the momentum exchange
       double v[3] = {fd[0], fd[1], fd[2]};
 #pragma unroll
@@ -102,10 +163,144 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
         for (int k = 0; k < 3; ++k) {
           double s = 0;
           for (int q = 0; q < nw; ++q) s += s_red[k][q];
-          L.drag[(size_t)w.brick * 3 + k] += s;
+          Lc->drag[(size_t)w.brick * 3 + k] += s;
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------- stream-collide, pipelined
+// Persistent variant: workgroup g processes items g, g+G, g+2G, ...  The records of a
+// chunk of its items are staged in LDS once; each thread (one node of the brick) issues
+// the population loads of its node in the next brick before it collides its node in
+// the current brick (two register buffers), so load latency overlaps arithmetic.
+constexpr int PIPE_RECS = 16;
+
+template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCArgs a) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+  constexpr int Q = nq<D>();
+  __shared__ ItemRec srec[PIPE_RECS];
+  __shared__ double s_red[3][4];
+  const int G = gridDim.x;
+  const int me = (a.remap && (G & 7) == 0) ? xcd_perm(blockIdx.x, G) : blockIdx.x;
+  if (me >= a.n_items) return;
+  const int cnt = (a.n_items - me + G - 1) / G;
+  const int n = threadIdx.x;
+  int x, y, z;
+  node_xyz<D>(n, x, y, z);
+  if (D == 3) z = __builtin_amdgcn_readfirstlane(z);  // one z-slice per wavefront
+  const BulkLane<D> bl(x, y, z);
+
+  struct Hdr {
+    int brick, level, thr, drag;
+    bool plain;
+  };
+  auto header = [&](int j) -> Hdr {
+    const uint64_t wi = *(const uint64_t *)&srec[j].w;
+    Hdr hd;
+    hd.brick = __builtin_amdgcn_readfirstlane((int)(uint32_t)wi);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(wi >> 32));
+    hd.level = hi & 0xff;
+    hd.thr = (hi >> 8) & 0xff;
+    hd.drag = (hi >> 16) & 0xff;
+    hd.plain = ((hi >> 24) & WI_PLAIN) != 0;
+    return hd;
+  };
+  // issue the loads of this thread's node in item j; false if the node is not updated
+  auto fetch = [&](int j, T (&h)[Q], uint32_t &cls, uint32_t &mask) -> bool {
+    const Hdr hd = header(j);
+    cptr<LevelStatic> Lc = cst(a.lev) + hd.level;
+    const Rsrc rs = buf_rsrc(a.src[hd.level], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
+    cls = CLS_FLUID | 2;
+    mask = 0;
+    if (!hd.plain) {
+      cls = Lc->cls[(size_t)hd.brick * BN + n];
+      if ((int)(cls & CLS_MODE) < hd.thr) return false;
+    }
+    if (!hd.plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW))) {
+      const LevelStatic &L = a.lev[hd.level];
+      mask = L.mask[(size_t)hd.brick * BN + n];
+      uint32_t mid[9], side[9];
+      auto nbu = [&](int k) { return __builtin_amdgcn_readfirstlane(srec[j].nbr[k]); };
+      bulk_offsets<D, ST>(nbu, z, mid, side);
+      auto nbo = [&](int q) {
+        const int nb = srec[j].nbr[q];
+        return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+      };
+      pull_links<D, ST>(rs, mid, side, bl, nbo, (uint32_t)hd.brick * brick_bytes<D, ST>(), x, y, z, n, cls, mask,
+                        Lc, h);
+    } else {
+      uint32_t mid[9], side[9];
+      auto nb = [&](int k) { return __builtin_amdgcn_readfirstlane(srec[j].nbr[k]); };
+      bulk_offsets<D, ST>(nb, z, mid, side);
+      pull_bulk<D, ST>(rs, mid, side, bl, h);
+    }
+    return true;
+  };
+  auto finish = [&](int j, T (&h)[Q], uint32_t cls, uint32_t mask, bool act) {
+    const Hdr hd = header(j);
+    cptr<LevelStatic> Lc = cst(a.lev) + hd.level;
+    double fd[3] = {0, 0, 0};
+    if (act) {
+      const uint32_t dbrick = (uint32_t)hd.brick * brick_bytes<D, ST>();
+      const Rsrc rd = buf_rsrc(a.dst[hd.level], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
+      T F[3] = {T(Lc->F[0]), T(Lc->F[1]), T(Lc->F[2])};
+      const float *force_p = Lc->force;
+      if (force_p) {
+        const float *fp = force_p + (size_t)hd.brick * D * BN + n;
+#pragma unroll
+        for (int c = 0; c < D; ++c) F[c] += T(fp[c * BN]) * T(Lc->fscale);
+      }
+      const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
+      const T g = kbc_collide<D, T>(h, T(Lc->beta), F, hf, [&](int i, T v) {
+        C::stb(rd, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)), v, T(wgt<D>(i)));
+      });
+      if ((a.flags & FL_GAMMA) && Lc->gamma) Lc->gamma[(size_t)hd.brick * BN + n] = (float)g;
+      if ((cls & CLS_DRAG) && (a.flags & FL_DRAG)) {
+        const S *ob = (const S *)a.dst[hd.level] + (size_t)hd.brick * Q * BN + n;
+        for (int i = 0; i < Q; ++i) {
+          if (!((mask >> (Q - 1 - i)) & 1u)) continue;
+          const double fi = wgt<D>(i) + (double)C::ld(ob + i * BN, T(wgt<D>(i)));
+          fd[0] += 2.0 * (double)cxo(i) * fi;
+          fd[1] += 2.0 * (double)cyo(i) * fi;
+          fd[2] += 2.0 * (double)czo<D>(i) * fi;
+        }
+      }
+    }
+    if (hd.drag && (a.flags & FL_DRAG)) {  // deterministic block reduction (uniform branch)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        for (int off = 32; off > 0; off >>= 1) fd[k] += __shfl_down(fd[k], off, 64);
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      if (lane == 0)
+        for (int k = 0; k < 3; ++k) s_red[k][wave] = fd[k];
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) Lc->drag[(size_t)hd.brick * 3 + k] += (s_red[k][0] + s_red[k][1]) + (s_red[k][2] + s_red[k][3]);
+      __syncthreads();
+    }
+  };
+  for (int c0 = 0; c0 < cnt; c0 += PIPE_RECS) {
+    const int m = cnt - c0 < PIPE_RECS ? cnt - c0 : PIPE_RECS;
+    for (int t = threadIdx.x; t < m * 32; t += blockDim.x) {
+      const int r = t >> 5, q = t & 31;
+      ((uint32_t *)srec)[t] = ((const uint32_t *)(a.items + me + (size_t)(c0 + r) * G))[q];
+    }
+    __syncthreads();
+    T hA[Q], hB[Q];
+    uint32_t cA = 0, mA = 0, cB = 0, mB = 0;
+    bool aA = fetch(0, hA, cA, mA), aB = false;
+    for (int j = 0; j < m; j += 2) {
+      if (j + 1 < m) aB = fetch(j + 1, hB, cB, mB);
+      finish(j, hA, cA, mA, aA);
+      if (j + 1 >= m) break;
+      if (j + 2 < m) aA = fetch(j + 2, hA, cA, mA);
+      finish(j + 1, hB, cB, mB, aB);
+    }
+    __syncthreads();
   }
 }
 
@@ -458,6 +653,10 @@ int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *s
   if (a.n_items <= 0) return 0;
   const int grid = cfg.grid > 0 ? cfg.grid : a.n_items;
   const int thr = cfg.threads > 0 ? cfg.threads : 256;
+  if (cfg.pipe) {  // persistent pipelined variant: one node per thread
+    ELBM_DISPATCH(D, st, (k_sc_pipe<DD, SS><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
+    return ck();
+  }
   if (cfg.occ >= 4)
     ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
   else

@@ -33,39 +33,77 @@ template <int D> __host__ __device__ constexpr double wgt(int i) {
 }
 
 // ---------------------------------------------------------------- storage codecs
+// Raw buffer resource over one level's population buffer: loads and stores address
+// it with a per-lane 32-bit offset plus a wave-uniform scalar offset (no 64-bit
+// address arithmetic per access); accesses past `bytes` read zero and are dropped.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ inline Rsrc buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
   typedef double S;
   typedef double T;
   __device__ static inline T ld(const S *p, T w) { return *p - w; }
   __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
+  __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T w) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0)) - w;
+  }
+  __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) V2;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, w + h), r, v, s, 0);
+  }
 };
 template <> struct Codec<ST_F32> {
   typedef float S;
   typedef float T;
   __device__ static inline T ld(const S *p, T w) { return *p - w; }
   __device__ static inline void st(S *p, T h, T w) { *p = w + h; }
+  __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T w) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0)) - w;
+  }
+  __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, w + h), r, v, s, 0);
+  }
 };
 template <> struct Codec<ST_F16S> {
   typedef uint16_t S;
   typedef float T;
-  __device__ static inline T ld(const S *p, T) { return __half2float(__ushort_as_half(*p)); }
-  __device__ static inline void st(S *p, T h, T) { *p = __half_as_ushort(__float2half_rn(h)); }
+  __device__ static inline T dec(uint16_t b) { return __half2float(__ushort_as_half(b)); }
+  __device__ static inline uint16_t enc(T h) { return __half_as_ushort(__float2half_rn(h)); }
+  __device__ static inline T ld(const S *p, T) { return dec(*p); }
+  __device__ static inline void st(S *p, T h, T) { *p = enc(h); }
+  __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T) {
+    return dec(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+  }
+  __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
+    __builtin_amdgcn_raw_buffer_store_b16(enc(h), r, v, s, 0);
+  }
 };
 template <> struct Codec<ST_BF16S> {
   typedef uint16_t S;
   typedef float T;
-  __device__ static inline T ld(const S *p, T) { return __uint_as_float(((uint32_t)*p) << 16); }
-  __device__ static inline void st(S *p, T h, T) {
+  __device__ static inline T dec(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+  __device__ static inline uint16_t enc(T h) {
     uint32_t b = __float_as_uint(h);
-    if ((b & 0x7fffffffu) > 0x7f800000u) {
-      *p = (uint16_t)0x7fc0u;
-    } else {
-      b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
-      *p = (uint16_t)(b >> 16);
-    }
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(b >> 16);
+  }
+  __device__ static inline T ld(const S *p, T) { return dec(*p); }
+  __device__ static inline void st(S *p, T h, T) { *p = enc(h); }
+  __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T) {
+    return dec(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+  }
+  __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
+    __builtin_amdgcn_raw_buffer_store_b16(enc(h), r, v, s, 0);
   }
 };
+
+template <int D, int ST> __device__ constexpr uint32_t brick_bytes() {
+  return (uint32_t)(nq<D>() * BN * sizeof(typename Codec<ST>::S));
+}
 
 // FP32 uses the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
 // division and square root.
@@ -305,6 +343,12 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
   return gamma;
 }
 
+// Tables that no kernel writes are read through the constant address space: with a
+// wave-uniform address that is a scalar load into SGPRs instead of a vector load
+// followed by readfirstlane.
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ inline cptr<T> cst(const T *p) { return (cptr<T>)p; }
+
 template <int D, typename T> __device__ inline void node_force(const LevelStatic &L, int brick, int n, T F[3]) {
   F[0] = T(L.F[0]);
   F[1] = T(L.F[1]);
@@ -417,28 +461,28 @@ template <int D> struct BulkLane {
   }
 };
 
+// Bulk pull.  mid[k]: byte offset of the neighbour brick at displacement code 9 + k
+// (same z-layer of bricks), side[k]: the brick layer below (z on the low brick face)
+// or above (z on the high face) -- z is uniform over a wavefront, so one side layer
+// suffices.  Offsets are wave-uniform scalars; lanes on x/y brick faces select
+// among them per population.
 template <int D, int ST>
-__device__ inline void pull_bulk(const char *__restrict__ srcb, const uint32_t (&off)[27], const BulkLane<D> &b,
-                                 typename Codec<ST>::T (&h)[nq<D>()]) {
+__device__ inline void pull_bulk(Rsrc src, const uint32_t (&mid)[9], const uint32_t (&side)[9],
+                                 const BulkLane<D> &b, typename Codec<ST>::T (&h)[nq<D>()]) {
   using C = Codec<ST>;
   using S = typename C::S;
   using T = typename C::T;
-  // z-plane of the source per direction (uniform): cz = +1 -> low neighbour when on
-  // the low face, cz = -1 -> high neighbour when on the high face
-  uint32_t oz[3][9];
-  static_for<0, 9>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    oz[0][k] = b.zlo ? off[k] : off[k + 9];
-    oz[1][k] = off[k + 9];
-    oz[2][k] = b.zhi ? off[k + 18] : off[k + 9];
-  });
   static_for<0, nq<D>()>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
-    constexpr int kz = 1 - cz;
     // the candidates are wave-uniform; readfirstlane keeps them scalar values so the
     // per-lane choice stays a register select (not an indexed load)
-    auto U = [&](int k) -> uint32_t { return __builtin_amdgcn_readfirstlane(oz[kz][k]); };
+    auto U = [&](int k) -> uint32_t {
+      uint32_t v = mid[k];
+      if constexpr (cz == 1) v = b.zlo ? side[k] : mid[k];
+      if constexpr (cz == -1) v = b.zhi ? side[k] : mid[k];
+      return __builtin_amdgcn_readfirstlane(v);
+    };
     auto Ox = [&](auto BY) -> uint32_t {
       constexpr int by = decltype(BY)::value;
       if constexpr (cx == 1) return b.xlo ? U(0 + 3 * by) : U(1 + 3 * by);
@@ -450,7 +494,89 @@ __device__ inline void pull_bulk(const char *__restrict__ srcb, const uint32_t (
     else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
     else base = Ox(Ic<1>());
     const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
-    h[i] = C::ld((const S *)(srcb + base + (uint32_t)((i * BN + loc) * (int)sizeof(S))), T(wgt<D>(i)));
+    h[i] = C::ldb(src, base + (uint32_t)(loc * (int)sizeof(S)), (uint32_t)(i * BN * (int)sizeof(S)), T(wgt<D>(i)));
+  });
+}
+
+// Pull of a node with special links (mask bit i set): bounce-back (CLS_LINKS) reads
+// the node's own population Q-1-i, an outflow link (CLS_OUTFLOW) reads population i one
+// node upstream of x - c_i (shift oshift back into the domain), an inlet link
+// (CLS_INLET) takes the inlet value.  The other links use the bulk addressing.  Every
+// address is formed with selects and every load is issued, so a wavefront keeps all
+// of its loads in flight.  nbo(code): byte offset of the neighbour brick of a
+// displacement code (an LDS table); own: byte offset of the node's brick; Lc: the
+// level's constants (scalar loads).
+template <int D, int ST, typename NBO>
+__device__ inline void pull_links(Rsrc src, const uint32_t (&md)[9], const uint32_t (&sd)[9],
+                                  const BulkLane<D> &b, NBO nbo, uint32_t own, int x, int y, int z, int n,
+                                  uint32_t cls, uint32_t mask, cptr<LevelStatic> Lc,
+                                  typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+  using Bk = Brick<D>;
+  constexpr int Q = nq<D>();
+  const bool bb = (cls & CLS_LINKS) != 0, inl = (cls & CLS_INLET) != 0, ofl = (cls & CLS_OUTFLOW) != 0;
+  uint32_t ov[Q];
+  const bool any_ofl = __builtin_amdgcn_ballot_w64(ofl) != 0;  // wave-uniform
+  if (any_ofl) {
+    const int ox = Lc->oshift[0], oy = Lc->oshift[1], oz = Lc->oshift[2];
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const int sx = x - cxo(i) - ox, sy = y - cyo(i) - oy, sz = z - czo<D>(i) - oz;
+      const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
+      const int loc = (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
+      ov[i] = nbo(code) + (uint32_t)((i * BN + loc) * (int)sizeof(S));
+    });
+  }
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
+    auto U = [&](int k) -> uint32_t {
+      uint32_t v = md[k];
+      if constexpr (cz == 1) v = b.zlo ? sd[k] : md[k];
+      if constexpr (cz == -1) v = b.zhi ? sd[k] : md[k];
+      return __builtin_amdgcn_readfirstlane(v);
+    };
+    auto Ox = [&](auto BY) -> uint32_t {
+      constexpr int by = decltype(BY)::value;
+      if constexpr (cx == 1) return b.xlo ? U(0 + 3 * by) : U(1 + 3 * by);
+      else if constexpr (cx == -1) return b.xhi ? U(2 + 3 * by) : U(1 + 3 * by);
+      else return U(1 + 3 * by);
+    };
+    uint32_t base;
+    if constexpr (cy == 1) base = b.ylo ? Ox(Ic<0>()) : Ox(Ic<1>());
+    else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
+    else base = Ox(Ic<1>());
+    const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
+    const bool hit = (mask >> i) & 1u;
+    uint32_t v = base + (uint32_t)((i * BN + loc) * (int)sizeof(S));
+    v = (bb && hit) ? own + (uint32_t)(((Q - 1 - i) * BN + n) * (int)sizeof(S)) : v;
+    if (any_ofl) v = (ofl && hit) ? ov[i] : v;
+    // the weights are symmetric (W_i = W_{Q-1-i}): one shift for every source
+    h[i] = C::ldb(src, v, 0u, T(wgt<D>(i)));
+  });
+  if (inl) {
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const T hv = T(Lc->hin[i]);
+      if ((mask >> i) & 1u) h[i] = hv;
+    });
+  }
+}
+
+// neighbour-brick byte offsets of the bulk pull; nbp(k): neighbour brick of
+// displacement code k (missing -> 0)
+template <int D, int ST, typename NB>
+__device__ inline void bulk_offsets(NB nbp, int z, uint32_t (&mid)[9], uint32_t (&side)[9]) {
+  using Bk = Brick<D>;
+  const int sl = (D == 3 && z == 0) ? 0 : ((D == 3 && z == Bk::BZ - 1) ? 18 : 9);
+  static_for<0, 9>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const int m = nbp(9 + k);
+    const int s = nbp(sl + k);
+    mid[k] = (uint32_t)(m < 0 ? 0 : m) * brick_bytes<D, ST>();
+    side[k] = (uint32_t)(s < 0 ? 0 : s) * brick_bytes<D, ST>();
   });
 }
 
@@ -466,9 +592,6 @@ __device__ inline int xcd_perm(int b, int G) {
   return (b & 7) * (G >> 3) + (b >> 3);
 }
 
-template <int D, int ST> __device__ constexpr uint32_t brick_bytes() {
-  return (uint32_t)(nq<D>() * BN * sizeof(typename Codec<ST>::S));
-}
 
 template <int D> __host__ __device__ constexpr int stage_width() { return D == 3 ? 32 : 12; }
 

@@ -85,7 +85,7 @@ def lib():
             "elbm_check": [P],
             "elbm_drag": [P, i32, dp, i64p, i32],
             "elbm_set_gamma_output": [P, i32],
-            "elbm_set_launch": [P, i32, i32, i32, i32, i32],
+            "elbm_set_launch": [P, i32, i32, i32, i32, i32, i32],
             "elbm_tune": [P, ctypes.c_char_p, i32],
             "elbm_get_launch": [P, P],
             "elbm_profile": [P, i32, dp, dp, i64p],
@@ -303,14 +303,14 @@ class Lattice:
     def set_gamma_output(self, enable=True):
         self._ck(lib().elbm_set_gamma_output(self._h, int(enable)))
 
-    def set_launch(self, use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, occupancy=1):
+    def set_launch(self, use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, occupancy=1, pipeline=0):
         self._ck(lib().elbm_set_launch(self._h, int(use_graph), int(wg_per_cu), int(xcd_remap), int(threads),
-                                       int(occupancy)))
+                                       int(occupancy), int(pipeline)))
 
     def get_launch(self):
-        cfg = (ctypes.c_int32 * 5)()
+        cfg = (ctypes.c_int32 * 6)()
         self._ck(lib().elbm_get_launch(self._h, cfg))
-        return dict(zip(("use_graph", "wg_per_cu", "xcd_remap", "threads", "occupancy"), list(cfg)))
+        return dict(zip(("use_graph", "wg_per_cu", "xcd_remap", "threads", "occupancy", "pipeline"), list(cfg)))
 
     def tune(self, cache_path=None, steps=3):
         self._ck(lib().elbm_tune(self._h, cache_path.encode() if cache_path else None, int(steps)))

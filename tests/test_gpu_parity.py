@@ -128,8 +128,10 @@ def test_mass_momentum_and_gamma_fp64(elbm):
 
 @pytest.mark.parametrize("launch", [dict(use_graph=0), dict(use_graph=1, wg_per_cu=2, xcd_remap=1, threads=128),
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=0, threads=64),
-                                    dict(use_graph=1, wg_per_cu=4, xcd_remap=1, threads=256, occupancy=4)],
-                         ids=["eager", "persistent-xcd", "oneperbrick", "regcap"])
+                                    dict(use_graph=1, wg_per_cu=4, xcd_remap=1, threads=256, occupancy=4),
+                                    dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=1),
+                                    dict(use_graph=0, wg_per_cu=3, xcd_remap=0, pipeline=1)],
+                         ids=["eager", "persistent-xcd", "oneperbrick", "regcap", "pipelined", "pipelined-eager"])
 def test_launch_configurations_bitwise_equal(elbm, launch):
     sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
     g0, o = pair(elbm, sp, "f32", 6)
@@ -159,6 +161,18 @@ def test_sphere_three_level_inlet_outflow_drag_fp32(elbm):
     assert sg == so == 80
     # momentum-exchange sums: FP32 populations, FP64 accumulation
     assert np.allclose(Fg, Fo, rtol=1e-5, atol=2e-6)
+
+
+def test_sphere_pipelined_bitwise_equal_with_drag(elbm):
+    """Special links (inlet, outflow, solid) and the drag reduction in the pipelined
+    stream-collide: same populations and drag as the one-brick-per-workgroup kernel."""
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12))
+    g0, _ = pair(elbm, sp, "f32", 5)
+    g1, _ = pair(elbm, sp, "f32", 5, launch=dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=1))
+    for l in range(sp.levels):
+        assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
+    assert np.array_equal(g0.drag(2)[0], g1.drag(2)[0])
 
 
 def test_forest_four_level_fp32(elbm):
