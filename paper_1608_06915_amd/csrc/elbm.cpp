@@ -84,6 +84,7 @@ struct Pair {
 struct Tick {
   int lmin;
   size_t sc_off, sc_n, gp_off, gp_n, tile_off, tile_n, ring_off, ring_n;
+  size_t sc_plain;  // the first sc_plain items of the tick are plain bricks
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -904,6 +905,10 @@ void build_schedule(elbm_ctx *c) {
       c->sc_all.insert(c->sc_all.end(), v.begin(), v.end());
     }
     tk.sc_n = c->sc_all.size() - tk.sc_off;
+    // plain bricks first (the pipelined stream-collide takes them)
+    auto mid = std::stable_partition(c->sc_all.begin() + tk.sc_off, c->sc_all.end(),
+                                     [](const WorkItem &w) { return (w.flags & WI_PLAIN) != 0; });
+    tk.sc_plain = (size_t)(mid - (c->sc_all.begin() + tk.sc_off));
     const int p0 = std::min(lmin, pL);
     tk.gp_off = gp_start[p0];
     tk.gp_n = gp_start[pL] - tk.gp_off;
@@ -1083,20 +1088,45 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
   LaunchCfg cfg;
   cfg.threads = c->threads;
   cfg.occ = c->occ;
-  cfg.pipe = c->pipe;
+  cfg.pipe = 0;
   cfg.grid = c->wg_per_cu > 0 ? std::min<int>((int)tk.sc_n, c->wg_per_cu * c->cu_count) : (int)tk.sc_n;
-  if (c->pipe) cfg.grid = std::min<int>((int)tk.sc_n, (c->wg_per_cu > 0 ? c->wg_per_cu : 3) * c->cu_count);
+  // pipelined mode: plain bricks in the persistent pipelined kernel, the others (walls,
+  // interface layers, inlet/outflow, drag) one brick per workgroup
+  SCArgs sp = s, sr = s;
+  LaunchCfg cp = cfg, cr = cfg;
+  const bool split = c->pipe && tk.sc_plain > 0;
+  if (split) {
+    sp.n_items = (int)tk.sc_plain;
+    cp.pipe = 1;
+    cp.grid = std::min<int>((int)tk.sc_plain, (c->wg_per_cu > 0 ? c->wg_per_cu : 2) * c->cu_count);
+    sr.items = s.items + tk.sc_plain;
+    sr.n_items = (int)(tk.sc_n - tk.sc_plain);
+    cr.grid = sr.n_items;
+    cr.occ = 1;
+    cr.threads = 256;
+  }
+  auto run = [&]() -> elbm_status {
+    if (split) {
+      LCK(c, launch_stream_collide(c->D, c->storage, sp, cp, main));
+      LCK(c, launch_stream_collide(c->D, c->storage, sr, cr, main));
+    } else {
+      LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
+    }
+    return ELBM_OK;
+  };
   if (c->timing) {
     hipEvent_t e0, e1;
     HIPCK(c, hipEventCreate(&e0));
     HIPCK(c, hipEventCreate(&e1));
     HIPCK(c, hipEventRecord(e0, main));
-    LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
+    elbm_status st = run();
+    if (st) return st;
     HIPCK(c, hipEventRecord(e1, main));
     c->tev.push_back(e0);
     c->tev.push_back(e1);
   } else {
-    LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
+    elbm_status st = run();
+    if (st) return st;
   }
   if (coupling && fork) {
     hipEvent_t ej = c->ev_join[(t - 1) % 64];

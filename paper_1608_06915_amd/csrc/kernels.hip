@@ -171,10 +171,12 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
 }
 
 // ---------------------------------------------------------------- stream-collide, pipelined
-// Persistent variant: workgroup g processes items g, g+G, g+2G, ...  The records of a
-// chunk of its items are staged in LDS once; each thread (one node of the brick) issues
-// the population loads of its node in the next brick before it collides its node in
-// the current brick (two register buffers), so load latency overlaps arithmetic.
+// Persistent variant for plain bricks (every node fluid, updated, plain links only):
+// workgroup g processes items g, g+G, g+2G, ...  The records of a chunk of its items
+// are staged in LDS once; each thread (one node of the brick) issues the loads of its
+// node in the next brick before it collides its node in the current brick (two
+// register buffers of raw stored values, decoded only when used), so load latency
+// overlaps the collision arithmetic.  Straight-line code: no per-node branches.
 constexpr int PIPE_RECS = 16;
 
 template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCArgs a) {
@@ -183,7 +185,6 @@ template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCA
   using T = typename C::T;
   constexpr int Q = nq<D>();
   __shared__ ItemRec srec[PIPE_RECS];
-  __shared__ double s_red[3][4];
   const int G = gridDim.x;
   const int me = (a.remap && (G & 7) == 0) ? xcd_perm(blockIdx.x, G) : blockIdx.x;
   if (me >= a.n_items) return;
@@ -193,95 +194,46 @@ template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCA
   node_xyz<D>(n, x, y, z);
   if (D == 3) z = __builtin_amdgcn_readfirstlane(z);  // one z-slice per wavefront
   const BulkLane<D> bl(x, y, z);
-
-  struct Hdr {
-    int brick, level, thr, drag;
-    bool plain;
-  };
-  auto header = [&](int j) -> Hdr {
-    const uint64_t wi = *(const uint64_t *)&srec[j].w;
-    Hdr hd;
-    hd.brick = __builtin_amdgcn_readfirstlane((int)(uint32_t)wi);
-    const int hi = __builtin_amdgcn_readfirstlane((int)(wi >> 32));
-    hd.level = hi & 0xff;
-    hd.thr = (hi >> 8) & 0xff;
-    hd.drag = (hi >> 16) & 0xff;
-    hd.plain = ((hi >> 24) & WI_PLAIN) != 0;
-    return hd;
-  };
-  // issue the loads of this thread's node in item j; false if the node is not updated
-  auto fetch = [&](int j, T (&h)[Q], uint32_t &cls, uint32_t &mask) -> bool {
-    const Hdr hd = header(j);
-    cptr<LevelStatic> Lc = cst(a.lev) + hd.level;
-    const Rsrc rs = buf_rsrc(a.src[hd.level], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
-    cls = CLS_FLUID | 2;
-    mask = 0;
-    if (!hd.plain) {
-      cls = Lc->cls[(size_t)hd.brick * BN + n];
-      if ((int)(cls & CLS_MODE) < hd.thr) return false;
-    }
-    if (!hd.plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW))) {
-      const LevelStatic &L = a.lev[hd.level];
-      mask = L.mask[(size_t)hd.brick * BN + n];
-      uint32_t mid[9], side[9];
-      auto nbu = [&](int k) { return __builtin_amdgcn_readfirstlane(srec[j].nbr[k]); };
-      bulk_offsets<D, ST>(nbu, z, mid, side);
-      auto nbo = [&](int q) {
-        const int nb = srec[j].nbr[q];
-        return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-      };
-      pull_links<D, ST>(rs, mid, side, bl, nbo, (uint32_t)hd.brick * brick_bytes<D, ST>(), x, y, z, n, cls, mask,
-                        Lc, h);
-    } else {
-      uint32_t mid[9], side[9];
-      auto nb = [&](int k) { return __builtin_amdgcn_readfirstlane(srec[j].nbr[k]); };
-      bulk_offsets<D, ST>(nb, z, mid, side);
-      pull_bulk<D, ST>(rs, mid, side, bl, h);
-    }
-    return true;
-  };
-  auto finish = [&](int j, T (&h)[Q], uint32_t cls, uint32_t mask, bool act) {
-    const Hdr hd = header(j);
-    cptr<LevelStatic> Lc = cst(a.lev) + hd.level;
-    double fd[3] = {0, 0, 0};
-    if (act) {
-      const uint32_t dbrick = (uint32_t)hd.brick * brick_bytes<D, ST>();
-      const Rsrc rd = buf_rsrc(a.dst[hd.level], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
-      T F[3] = {T(Lc->F[0]), T(Lc->F[1]), T(Lc->F[2])};
-      const float *force_p = Lc->force;
-      if (force_p) {
-        const float *fp = force_p + (size_t)hd.brick * D * BN + n;
+  auto level_of = [&](int j) { return __builtin_amdgcn_readfirstlane((int)srec[j].w.level); };
+  auto brick_of = [&](int j) { return __builtin_amdgcn_readfirstlane((int)srec[j].w.brick); };
+  // all loads of item j (populations and the node's force field) are issued together:
+  // the memory counter completes in order, so a later load would wait for the prefetch
+  auto fetch = [&](int j, S (&r)[Q], float (&rf)[3]) {
+    const int l = level_of(j);
+    cptr<LevelStatic> Lc = cst(a.lev) + l;
+    const Rsrc rs = buf_rsrc(a.src[l], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
+    uint32_t mid[9], side[9];
+    bulk_offsets<D, ST>([&](int k) { return __builtin_amdgcn_readfirstlane(srec[j].nbr[k]); }, z, mid, side);
+    pull_bulk_with<D, ST>(mid, side, bl, [&](int i, uint32_t v, uint32_t s) { r[i] = C::ldr(rs, v, s); });
+    rf[0] = rf[1] = rf[2] = 0.f;
+    const float *force_p = Lc->force;
+    if (force_p) {
+      const Rsrc rfc = buf_rsrc(force_p, (uint32_t)Lc->nbricks * D * BN * 4u);
+      const uint32_t fb = (uint32_t)brick_of(j) * (uint32_t)(D * BN * 4);
 #pragma unroll
-        for (int c = 0; c < D; ++c) F[c] += T(fp[c * BN]) * T(Lc->fscale);
-      }
-      const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
-      const T g = kbc_collide<D, T>(h, T(Lc->beta), F, hf, [&](int i, T v) {
-        C::stb(rd, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)), v, T(wgt<D>(i)));
-      });
-      if ((a.flags & FL_GAMMA) && Lc->gamma) Lc->gamma[(size_t)hd.brick * BN + n] = (float)g;
-      if ((cls & CLS_DRAG) && (a.flags & FL_DRAG)) {
-        const S *ob = (const S *)a.dst[hd.level] + (size_t)hd.brick * Q * BN + n;
-        for (int i = 0; i < Q; ++i) {
-          if (!((mask >> (Q - 1 - i)) & 1u)) continue;
-          const double fi = wgt<D>(i) + (double)C::ld(ob + i * BN, T(wgt<D>(i)));
-          fd[0] += 2.0 * (double)cxo(i) * fi;
-          fd[1] += 2.0 * (double)cyo(i) * fi;
-          fd[2] += 2.0 * (double)czo<D>(i) * fi;
-        }
-      }
+      for (int c = 0; c < D; ++c)
+        rf[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rfc, (uint32_t)(n * 4),
+                                                                               fb + (uint32_t)(c * BN * 4), 0));
     }
-    if (hd.drag && (a.flags & FL_DRAG)) {  // deterministic block reduction (uniform branch)
+  };
+  auto finish = [&](int j, const S (&r)[Q], const float (&rf)[3]) {
+    const int l = level_of(j), brick = brick_of(j);
+    cptr<LevelStatic> Lc = cst(a.lev) + l;
+    T h[Q];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        for (int off = 32; off > 0; off >>= 1) fd[k] += __shfl_down(fd[k], off, 64);
-      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-      if (lane == 0)
-        for (int k = 0; k < 3; ++k) s_red[k][wave] = fd[k];
-      __syncthreads();
-      if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) Lc->drag[(size_t)hd.brick * 3 + k] += (s_red[k][0] + s_red[k][1]) + (s_red[k][2] + s_red[k][3]);
-      __syncthreads();
+    for (int i = 0; i < Q; ++i) h[i] = C::dec(r[i], T(wgt<D>(i)));
+    const uint32_t dbrick = (uint32_t)brick * brick_bytes<D, ST>();
+    const Rsrc rd = buf_rsrc(a.dst[l], (uint32_t)Lc->nbricks * brick_bytes<D, ST>());
+    T F[3] = {T(Lc->F[0]), T(Lc->F[1]), T(Lc->F[2])};
+    if (Lc->force) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) F[c] += T(rf[c]) * T(Lc->fscale);
     }
+    const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
+    const T g = kbc_collide<D, T>(h, T(Lc->beta), F, hf, [&](int i, T v) {
+      C::stb(rd, (uint32_t)(n * (int)sizeof(S)), dbrick + (uint32_t)(i * BN * (int)sizeof(S)), v, T(wgt<D>(i)));
+    });
+    if ((a.flags & FL_GAMMA) && Lc->gamma) Lc->gamma[(size_t)brick * BN + n] = (float)g;
   };
   for (int c0 = 0; c0 < cnt; c0 += PIPE_RECS) {
     const int m = cnt - c0 < PIPE_RECS ? cnt - c0 : PIPE_RECS;
@@ -290,15 +242,15 @@ template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCA
       ((uint32_t *)srec)[t] = ((const uint32_t *)(a.items + me + (size_t)(c0 + r) * G))[q];
     }
     __syncthreads();
-    T hA[Q], hB[Q];
-    uint32_t cA = 0, mA = 0, cB = 0, mB = 0;
-    bool aA = fetch(0, hA, cA, mA), aB = false;
+    S hA[Q], hB[Q];
+    float fA[3], fB[3];
+    fetch(0, hA, fA);
     for (int j = 0; j < m; j += 2) {
-      if (j + 1 < m) aB = fetch(j + 1, hB, cB, mB);
-      finish(j, hA, cA, mA, aA);
+      if (j + 1 < m) fetch(j + 1, hB, fB);
+      finish(j, hA, fA);
       if (j + 1 >= m) break;
-      if (j + 2 < m) aA = fetch(j + 2, hA, cA, mA);
-      finish(j + 1, hB, cB, mB, aB);
+      if (j + 2 < m) fetch(j + 2, hA, fA);
+      finish(j + 1, hB, fB);
     }
     __syncthreads();
   }
@@ -653,7 +605,7 @@ int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *s
   if (a.n_items <= 0) return 0;
   const int grid = cfg.grid > 0 ? cfg.grid : a.n_items;
   const int thr = cfg.threads > 0 ? cfg.threads : 256;
-  if (cfg.pipe) {  // persistent pipelined variant: one node per thread
+  if (cfg.pipe) {  // persistent pipelined variant for plain bricks: one node per thread
     ELBM_DISPATCH(D, st, (k_sc_pipe<DD, SS><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
     return ck();
   }

@@ -50,6 +50,10 @@ template <> struct Codec<ST_F64> {
   __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T w) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0)) - w;
   }
+  __device__ static inline S ldr(Rsrc r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+  }
+  __device__ static inline T dec(S x, T w) { return x - w; }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) V2;
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, w + h), r, v, s, 0);
@@ -63,6 +67,10 @@ template <> struct Codec<ST_F32> {
   __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T w) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0)) - w;
   }
+  __device__ static inline S ldr(Rsrc r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+  }
+  __device__ static inline T dec(S x, T w) { return x - w; }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, w + h), r, v, s, 0);
   }
@@ -70,34 +78,42 @@ template <> struct Codec<ST_F32> {
 template <> struct Codec<ST_F16S> {
   typedef uint16_t S;
   typedef float T;
-  __device__ static inline T dec(uint16_t b) { return __half2float(__ushort_as_half(b)); }
-  __device__ static inline uint16_t enc(T h) { return __half_as_ushort(__float2half_rn(h)); }
-  __device__ static inline T ld(const S *p, T) { return dec(*p); }
-  __device__ static inline void st(S *p, T h, T) { *p = enc(h); }
+  __device__ static inline T unpack(uint16_t b) { return __half2float(__ushort_as_half(b)); }
+  __device__ static inline uint16_t pack(T h) { return __half_as_ushort(__float2half_rn(h)); }
+  __device__ static inline T ld(const S *p, T) { return unpack(*p); }
+  __device__ static inline void st(S *p, T h, T) { *p = pack(h); }
+  __device__ static inline S ldr(Rsrc r, uint32_t v, uint32_t s) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+  }
+  __device__ static inline T dec(S x, T) { return unpack(x); }
   __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T) {
-    return dec(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+    return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
-    __builtin_amdgcn_raw_buffer_store_b16(enc(h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, 0);
   }
 };
 template <> struct Codec<ST_BF16S> {
   typedef uint16_t S;
   typedef float T;
-  __device__ static inline T dec(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-  __device__ static inline uint16_t enc(T h) {
+  __device__ static inline T unpack(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+  __device__ static inline uint16_t pack(T h) {
     uint32_t b = __float_as_uint(h);
     if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
     b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
     return (uint16_t)(b >> 16);
   }
-  __device__ static inline T ld(const S *p, T) { return dec(*p); }
-  __device__ static inline void st(S *p, T h, T) { *p = enc(h); }
+  __device__ static inline T ld(const S *p, T) { return unpack(*p); }
+  __device__ static inline void st(S *p, T h, T) { *p = pack(h); }
+  __device__ static inline S ldr(Rsrc r, uint32_t v, uint32_t s) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+  }
+  __device__ static inline T dec(S x, T) { return unpack(x); }
   __device__ static inline T ldb(Rsrc r, uint32_t v, uint32_t s, T) {
-    return dec(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+    return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
-    __builtin_amdgcn_raw_buffer_store_b16(enc(h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, 0);
   }
 };
 
@@ -466,12 +482,10 @@ template <int D> struct BulkLane {
 // or above (z on the high face) -- z is uniform over a wavefront, so one side layer
 // suffices.  Offsets are wave-uniform scalars; lanes on x/y brick faces select
 // among them per population.
-template <int D, int ST>
-__device__ inline void pull_bulk(Rsrc src, const uint32_t (&mid)[9], const uint32_t (&side)[9],
-                                 const BulkLane<D> &b, typename Codec<ST>::T (&h)[nq<D>()]) {
-  using C = Codec<ST>;
-  using S = typename C::S;
-  using T = typename C::T;
+template <int D, int ST, typename LD>
+__device__ inline void pull_bulk_with(const uint32_t (&mid)[9], const uint32_t (&side)[9], const BulkLane<D> &b,
+                                      LD ld) {
+  using S = typename Codec<ST>::S;
   static_for<0, nq<D>()>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
@@ -494,8 +508,16 @@ __device__ inline void pull_bulk(Rsrc src, const uint32_t (&mid)[9], const uint3
     else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
     else base = Ox(Ic<1>());
     const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
-    h[i] = C::ldb(src, base + (uint32_t)(loc * (int)sizeof(S)), (uint32_t)(i * BN * (int)sizeof(S)), T(wgt<D>(i)));
+    ld(i, base + (uint32_t)(loc * (int)sizeof(S)), (uint32_t)(i * BN * (int)sizeof(S)));
   });
+}
+
+template <int D, int ST>
+__device__ inline void pull_bulk(Rsrc src, const uint32_t (&mid)[9], const uint32_t (&side)[9],
+                                 const BulkLane<D> &b, typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  pull_bulk_with<D, ST>(mid, side, b, [&](int i, uint32_t v, uint32_t s) { h[i] = C::ldb(src, v, s, T(wgt<D>(i))); });
 }
 
 // Pull of a node with special links (mask bit i set): bounce-back (CLS_LINKS) reads
@@ -506,17 +528,14 @@ __device__ inline void pull_bulk(Rsrc src, const uint32_t (&mid)[9], const uint3
 // of its loads in flight.  nbo(code): byte offset of the neighbour brick of a
 // displacement code (an LDS table); own: byte offset of the node's brick; Lc: the
 // level's constants (scalar loads).
-template <int D, int ST, typename NBO>
-__device__ inline void pull_links(Rsrc src, const uint32_t (&md)[9], const uint32_t (&sd)[9],
-                                  const BulkLane<D> &b, NBO nbo, uint32_t own, int x, int y, int z, int n,
-                                  uint32_t cls, uint32_t mask, cptr<LevelStatic> Lc,
-                                  typename Codec<ST>::T (&h)[nq<D>()]) {
-  using C = Codec<ST>;
-  using S = typename C::S;
-  using T = typename C::T;
+template <int D, int ST, typename NBO, typename LD>
+__device__ inline void pull_links_with(const uint32_t (&md)[9], const uint32_t (&sd)[9], const BulkLane<D> &b,
+                                       NBO nbo, uint32_t own, int x, int y, int z, int n, uint32_t cls,
+                                       uint32_t mask, cptr<LevelStatic> Lc, LD ld) {
+  using S = typename Codec<ST>::S;
   using Bk = Brick<D>;
   constexpr int Q = nq<D>();
-  const bool bb = (cls & CLS_LINKS) != 0, inl = (cls & CLS_INLET) != 0, ofl = (cls & CLS_OUTFLOW) != 0;
+  const bool bb = (cls & CLS_LINKS) != 0, ofl = (cls & CLS_OUTFLOW) != 0;
   uint32_t ov[Q];
   const bool any_ofl = __builtin_amdgcn_ballot_w64(ofl) != 0;  // wave-uniform
   if (any_ofl) {
@@ -554,15 +573,31 @@ __device__ inline void pull_links(Rsrc src, const uint32_t (&md)[9], const uint3
     v = (bb && hit) ? own + (uint32_t)(((Q - 1 - i) * BN + n) * (int)sizeof(S)) : v;
     if (any_ofl) v = (ofl && hit) ? ov[i] : v;
     // the weights are symmetric (W_i = W_{Q-1-i}): one shift for every source
-    h[i] = C::ldb(src, v, 0u, T(wgt<D>(i)));
+    ld(i, v, 0u);
   });
-  if (inl) {
-    static_for<0, Q>([&](auto I) {
+}
+
+// inlet links take the inlet populations (after the loads of pull_links_with)
+template <int D, typename T>
+__device__ inline void apply_inlet(uint32_t cls, uint32_t mask, cptr<LevelStatic> Lc, T (&h)[nq<D>()]) {
+  if (cls & CLS_INLET) {
+    static_for<0, nq<D>()>([&](auto I) {
       constexpr int i = decltype(I)::value;
       const T hv = T(Lc->hin[i]);
       if ((mask >> i) & 1u) h[i] = hv;
     });
   }
+}
+
+template <int D, int ST, typename NBO>
+__device__ inline void pull_links(Rsrc src, const uint32_t (&md)[9], const uint32_t (&sd)[9], const BulkLane<D> &b,
+                                  NBO nbo, uint32_t own, int x, int y, int z, int n, uint32_t cls, uint32_t mask,
+                                  cptr<LevelStatic> Lc, typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  pull_links_with<D, ST>(md, sd, b, nbo, own, x, y, z, n, cls, mask, Lc,
+                         [&](int i, uint32_t v, uint32_t s) { h[i] = C::ldb(src, v, s, T(wgt<D>(i))); });
+  apply_inlet<D, T>(cls, mask, Lc, h);
 }
 
 // neighbour-brick byte offsets of the bulk pull; nbp(k): neighbour brick of
