@@ -434,9 +434,17 @@ template <int D, int ST> __global__ __launch_bounds__(64) void k_adj_couple(AdjC
   if ((int)blockIdx.x < a.n_tiles) {
     const CTile t = a.tiles[blockIdx.x];
     const V *stage = (const V *)a.stage;
+    // entries packed to 4 bytes: tile-local row (16 bits) and the weight in FP16 (the
+    // weights are products of -1/16, 9/16 and 1: exact in FP16)
+    constexpr int SL = lds_stride<D, T>();
+    uint32_t *ents = (uint32_t *)(rows + (size_t)a.lds_rows * SL);
     for (int k = threadIdx.x; k < t.npt * (SW / 4); k += blockDim.x) {
       const int r = k / (SW / 4), q = k - r * (SW / 4);
-      ((V *)rows)[k] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+    }
+    for (int k = threadIdx.x; k < t.ne; k += blockDim.x) {
+      const StencilEntry s = a.sten[t.e0 + k];
+      ents[k] = (uint32_t)s.slot | ((uint32_t)__half_as_ushort(__float2half_rn(s.w)) << 16);
     }
     __syncthreads();
     for (int it = threadIdx.x; it < t.nitem; it += blockDim.x) {
@@ -444,10 +452,10 @@ template <int D, int ST> __global__ __launch_bounds__(64) void k_adj_couple(AdjC
       T acc[SW];
 #pragma unroll
       for (int v = 0; v < SW; ++v) acc[v] = 0;
-      for (int e = c.a; e < c.a + c.b; ++e) {
-        const StencilEntry s = a.sten[e];
-        const T w = T(s.w);
-        const V *row = (const V *)(rows + s.slot * SW);
+      for (int e = c.a - t.e0; e < c.a - t.e0 + c.b; ++e) {
+        const uint32_t s = ents[e];
+        const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
+        const V *row = (const V *)(rows + (s & 0xffffu) * SL);
 #pragma unroll
         for (int v = 0; v < SW / 4; ++v) {
           const V r = row[v];
@@ -744,7 +752,7 @@ int launch_adj_transpose(int D, int st, const AdjArgs &a, void *stream) {
 int launch_adj_couple(int D, int st, const AdjCoupleArgs &a, void *stream) {
   const int grid = a.c.n_tiles + (a.c.n_ring + 63) / 64;
   if (grid <= 0) return 0;
-  const size_t lds = (size_t)a.c.lds_rows * stage_row_width(D) * (st == ST_F64 ? 8 : 4);
+  const size_t lds = (size_t)a.c.lds_rows * couple_lds_stride(D, st) * (st == ST_F64 ? 8 : 4) + (size_t)a.c.lds_ents * 4;
   ELBM_ADJ_DISPATCH(D, st, (k_adj_couple<DD, SS><<<grid, 64, lds, (hipStream_t)stream>>>(a)));
   return ack();
 }

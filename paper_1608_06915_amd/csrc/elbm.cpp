@@ -108,7 +108,7 @@ struct elbm_ctx {
   std::vector<CTile> tiles_all;
   std::vector<int32_t> tile_rows_all;
   std::vector<StencilEntry> sten, tsten_all;
-  int lds_rows = 1;
+  int lds_rows = 1, lds_ents = 1;
   int stage_cols = 0;
   bool finalized = false, bound = false;
   std::string err;
@@ -778,7 +778,7 @@ elbm_status build_pairs(elbm_ctx *c) {
     // tiles: fine interface nodes of one brick, longest stencils first (uniform loop
     // counts within a wavefront), split when the distinct rows exceed the LDS budget
     {
-      const int maxr = couple_max_rows(D, c->storage);
+      const int maxr = couple_max_rows(D, c->storage), maxe = couple_max_entries();
       std::vector<CItem> its = P.items;
       std::stable_sort(its.begin(), its.end(), [](const CItem &x, const CItem &y) {
         return x.brick != y.brick ? x.brick < y.brick : x.b > y.b;
@@ -791,12 +791,16 @@ elbm_status build_pairs(elbm_ctx *c) {
         t.pt0 = (int32_t)P.tile_rows.size();
         t.nitem = 0;
         t.npt = 0;
+        t.e0 = (int32_t)P.tsten.size();
+        t.ne = 0;
         std::unordered_map<int32_t, int32_t> local;
         while (k < its.size() && its[k].brick == br) {
           const CItem &it = its[k];
           int add = 0;
           for (int e = it.a; e < it.a + it.b; ++e) add += local.count(c->sten[e].slot) ? 0 : 1;
-          if (t.npt + add > maxr && t.nitem > 0) break;  // close the tile, same brick continues
+          // close the tile (the same brick continues) when its rows or entries exceed LDS
+          if ((t.npt + add > maxr || t.ne + it.b > maxe) && t.nitem > 0) break;
+          t.ne += it.b;
           CItem ti = it;
           ti.a = (int32_t)P.tsten.size();
           for (int e = it.a; e < it.a + it.b; ++e) {
@@ -819,6 +823,7 @@ elbm_status build_pairs(elbm_ctx *c) {
           ++k;
         }
         c->lds_rows = std::max(c->lds_rows, (int)t.npt);
+        c->lds_ents = std::max(c->lds_ents, (int)t.ne);
         P.tiles.push_back(t);
       }
     }
@@ -873,6 +878,7 @@ void build_schedule(elbm_ctx *c) {
     for (CTile t : P.tiles) {
       t.item0 += item_base;
       t.pt0 += row_base;
+      t.e0 += sten_base;
       c->tiles_all.push_back(t);
     }
     for (CItem it : P.titems) {
@@ -1057,6 +1063,7 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     a.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
     a.n_tiles = (int)tk.tile_n;
     a.lds_rows = c->lds_rows;
+    a.lds_ents = c->lds_ents;
     a.tile_rows = (const int32_t *)(c->ws + c->o_trows);
     a.items = (const CItem *)(c->ws + c->o_fine);
     a.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;
@@ -1368,6 +1375,7 @@ elbm_status adj_tick(elbm_ctx *c, int k, int t) {
     ca.c.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
     ca.c.n_tiles = (int)tk.tile_n;
     ca.c.lds_rows = c->lds_rows;
+    ca.c.lds_ents = c->lds_ents;
     ca.c.tile_rows = (const int32_t *)(c->ws + c->o_trows);
     ca.c.items = (const CItem *)(c->ws + c->o_fine);
     ca.c.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;

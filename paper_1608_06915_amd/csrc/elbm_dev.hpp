@@ -75,6 +75,7 @@ struct StencilEntry {
 struct CTile {  // fine interface nodes of one brick whose stencils share staged rows
   int32_t item0, nitem;  // fine interface items
   int32_t pt0, npt;      // staged rows copied to LDS
+  int32_t e0, ne;        // the items' stencil entries (contiguous), copied to LDS
 };
 
 struct LevelStatic {  // device-resident per-level constants and table pointers
@@ -128,6 +129,7 @@ struct CoupleArgs {
   const CTile *tiles;     // fine interface tiles of the tick
   int32_t n_tiles;
   int32_t lds_rows;       // rows of the dynamic LDS buffer
+  int32_t lds_ents;       // stencil entries of the dynamic LDS buffer (after the rows)
   const int32_t *tile_rows;  // staged row index per tile row
   const CItem *items;     // fine interface items (kind 0) referenced by the tiles
   const CItem *ring;      // coarse ring items (kind 1) of the tick
@@ -226,7 +228,9 @@ int launch_reduce(int D, int st, void *const *pops, const LevelStatic *lev_dev, 
 int launch_force_scatter(int D, float *force, const double *F, int nbricks, const int32_t *borg, Dims box,
                          void *stream);
 int stage_row_width(int D);
+int couple_lds_stride(int D, int st);
 int couple_max_rows(int D, int st);
+int couple_max_entries();
 int launch_zero(void *p, size_t bytes, void *stream);
 int launch_adj_collide(int D, int st, const AdjArgs &a, void *stream);
 int launch_adj_couple(int D, int st, const AdjCoupleArgs &a, void *stream);

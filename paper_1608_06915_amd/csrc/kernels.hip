@@ -303,7 +303,7 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherA
 // its tensor stencil from LDS.  Ring nodes are handled by the trailing workgroups.
 constexpr int COUPLE_LDS_BYTES = 48 * 1024;
 template <int D, typename T> __host__ __device__ constexpr int couple_rows() {
-  return COUPLE_LDS_BYTES / (stage_width<D>() * (int)sizeof(T));
+  return COUPLE_LDS_BYTES / (lds_stride<D, T>() * (int)sizeof(T));
 }
 
 template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &a, const CItem &c,
@@ -321,7 +321,7 @@ template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &
   if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
 }
 
-template <int D, int ST> __global__ __launch_bounds__(64) void k_couple(CoupleArgs a) {
+template <int D, int ST> __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
   using C = Codec<ST>;
   using T = typename C::T;
   using V = typename V4<T>::type;
@@ -332,9 +332,17 @@ template <int D, int ST> __global__ __launch_bounds__(64) void k_couple(CoupleAr
   if ((int)blockIdx.x < a.n_tiles) {
     const CTile t = a.tiles[blockIdx.x];
     const V *stage = (const V *)a.stage;
+    // entries packed to 4 bytes: tile-local row (16 bits) and the weight in FP16 (the
+    // weights are products of -1/16, 9/16 and 1: exact in FP16)
+    constexpr int SL = lds_stride<D, T>();
+    uint32_t *ents = (uint32_t *)(rows + (size_t)a.lds_rows * SL);
     for (int k = threadIdx.x; k < t.npt * (SW / 4); k += blockDim.x) {
       const int r = k / (SW / 4), q = k - r * (SW / 4);
-      ((V *)rows)[k] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+    }
+    for (int k = threadIdx.x; k < t.ne; k += blockDim.x) {
+      const StencilEntry s = a.sten[t.e0 + k];
+      ents[k] = (uint32_t)s.slot | ((uint32_t)__half_as_ushort(__float2half_rn(s.w)) << 16);
     }
     __syncthreads();
     for (int it = threadIdx.x; it < t.nitem; it += blockDim.x) {
@@ -342,10 +350,10 @@ template <int D, int ST> __global__ __launch_bounds__(64) void k_couple(CoupleAr
       T acc[SW];
 #pragma unroll
       for (int v = 0; v < SW; ++v) acc[v] = 0;
-      for (int e = c.a; e < c.a + c.b; ++e) {
-        const StencilEntry s = a.sten[e];
-        const T w = T(s.w);
-        const V *row = (const V *)(rows + s.slot * SW);
+      for (int e = c.a - t.e0; e < c.a - t.e0 + c.b; ++e) {
+        const uint32_t s = ents[e];
+        const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
+        const V *row = (const V *)(rows + (s & 0xffffu) * SL);
 #pragma unroll
         for (int v = 0; v < SW / 4; ++v) {
           const V r = row[v];
@@ -625,6 +633,15 @@ int launch_gather(int D, int st, const GatherArgs &a, void *stream) {
 
 int stage_row_width(int D) { return D == 3 ? stage_width<3>() : stage_width<2>(); }
 
+int couple_lds_stride(int D, int st) {
+  const bool dbl = st == ST_F64;
+  if (D == 2) return dbl ? lds_stride<2, double>() : lds_stride<2, float>();
+  return dbl ? lds_stride<3, double>() : lds_stride<3, float>();
+}
+
+// stencil entries of one tile staged in LDS (8 bytes each)
+int couple_max_entries() { return 2048; }
+
 int couple_max_rows(int D, int st) {
   const bool dbl = st == ST_F64;
   if (D == 2) return dbl ? couple_rows<2, double>() : couple_rows<2, float>();
@@ -632,13 +649,13 @@ int couple_max_rows(int D, int st) {
 }
 
 int launch_couple(int D, int st, const CoupleArgs &a, void *stream) {
-  // one wavefront per tile (a tile holds about one brick layer of interface nodes);
-  // LDS sized to the largest tile, so several tiles share a CU
-  const int ring_blocks = (a.n_ring + 63) / 64;
+  // one workgroup of two wavefronts per tile (a tile holds one or two brick layers of
+  // interface nodes); LDS sized to the largest tile, so several tiles share a CU
+  const int ring_blocks = (a.n_ring + 127) / 128;
   const int grid = a.n_tiles + ring_blocks;
   if (grid <= 0) return 0;
-  const size_t lds = (size_t)a.lds_rows * stage_row_width(D) * (st == ST_F64 ? 8 : 4);
-  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, 64, lds, (hipStream_t)stream>>>(a)));
+  const size_t lds = (size_t)a.lds_rows * couple_lds_stride(D, st) * (st == ST_F64 ? 8 : 4) + (size_t)a.lds_ents * 4;
+  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, 128, lds, (hipStream_t)stream>>>(a)));
   return ck();
 }
 

@@ -629,6 +629,15 @@ __device__ inline int xcd_perm(int b, int G) {
 
 
 template <int D> __host__ __device__ constexpr int stage_width() { return D == 3 ? 32 : 12; }
+// row stride of staged rows in LDS: a row that is a multiple of 128 bytes (all banks)
+// gets one vector (4 elements) of padding, so that the rows that different lanes read
+// start in different bank groups; rows are copied and read as 4-element vectors
+template <int D, typename T> __host__ __device__ constexpr int lds_stride() {
+  return (stage_width<D>() * (int)sizeof(T)) % 128 == 0 ? stage_width<D>() + 4 : stage_width<D>();
+}
+static_assert(lds_stride<3, float>() % 4 == 0 && lds_stride<3, double>() % 4 == 0 &&
+                  lds_stride<2, float>() % 4 == 0 && lds_stride<2, double>() % 4 == 0,
+              "staged rows are accessed as 4-element vectors");
 
 template <typename T> struct V4;
 template <> struct V4<float> {

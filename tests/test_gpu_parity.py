@@ -110,6 +110,19 @@ def test_taylor_green_two_level_fp64_full_horizon(elbm):
     assert amp == pytest.approx(ref, rel=1e-2)
 
 
+def test_sphere_three_level_fp64(elbm):
+    """D3Q27 FP64, three nested levels with inlet, outflow and a sphere: every population
+    of every level to rounding order after 6 coarse steps."""
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12), noise=1e-3)
+    g, o = pair(elbm, sp, "f64", 6)
+    assert max_df(g, o, sp) < 1e-13
+    Fg, _ = g.drag(2)
+    Fo, _ = o.drag(2)
+    # momentum-exchange sums cancel O(1) terms: absolute error relative to |F|
+    assert np.max(np.abs(Fg - Fo)) < 1e-12 * np.max(np.abs(Fo))
+
+
 def test_mass_momentum_and_gamma_fp64(elbm):
     sp = synth.tgv2d(32, (8, 24), 0.04, 0.02, noise=1e-3)
     g, o = pair(elbm, sp, "f64", 20, gamma=True)
