@@ -306,11 +306,13 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_collide(Ad
   const LevelStatic &L = a.lev[wl];
   const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
   cptr<int32_t> nbc = cst(L.nbr) + (size_t)w.brick * 27;
-  auto boff = [&](int code) {
-    const int nb = nbp[code];
-    return (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
-  };
   const char *__restrict__ srcb = (const char *)a.src[wl];
+  __shared__ uint32_t s_nbo[27];
+  if (threadIdx.x < 27) {
+    const int nb = nbp[threadIdx.x];
+    s_nbo[threadIdx.x] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+  }
+  __syncthreads();
   const T *__restrict__ lam = (const T *)a.lam[wl] + (size_t)w.brick * Q * BN;
   T *__restrict__ lg = (T *)a.lg[wl] + (size_t)w.brick * Q * BN;
   T *__restrict__ lF = a.lF[wl] ? (T *)a.lF[wl] + (size_t)w.brick * D * BN : nullptr;
@@ -327,15 +329,19 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_collide(Ad
     if (D == 3) z = __builtin_amdgcn_readfirstlane(z);
     T h[Q];
     uint32_t mask = 0;
-    if (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) {
-      mask = L.mask[(size_t)w.brick * BN + n];
-      const Lane<D> ln(x, y, z);
-      pull_special<D, ST>(srcb, boff, ln, n, cls, mask, L, h);
-    } else {
+    {
       uint32_t mid[9], side[9];
       bulk_offsets<D, ST>([&](int q) { return (int)nbc[q]; }, z, mid, side);
       const BulkLane<D> bl(x, y, z);
-      pull_bulk<D, ST>(buf_rsrc(srcb, (uint32_t)L.nbricks * brick_bytes<D, ST>()), mid, side, bl, h);
+      const Rsrc rs = buf_rsrc(srcb, (uint32_t)L.nbricks * brick_bytes<D, ST>());
+      const bool special = (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) != 0;
+      if (__builtin_amdgcn_ballot_w64(special) != 0) {
+        mask = special ? L.mask[(size_t)w.brick * BN + n] : 0u;
+        pull_links<D, ST>(rs, mid, side, bl, [&](int q) { return s_nbo[q]; }, (uint32_t)w.brick * brick_bytes<D, ST>(),
+                          x, y, z, n, cls, mask, cst(a.lev) + wl, h);
+      } else {
+        pull_bulk<D, ST>(rs, mid, side, bl, h);
+      }
     }
     T l[Q];
 #pragma unroll

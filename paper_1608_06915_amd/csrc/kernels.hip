@@ -104,8 +104,11 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
       if (D == 3) z = __builtin_amdgcn_readfirstlane(z);  // one z-slice per wavefront
       T h[Q];
       uint32_t mask = 0;
-      if (!plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW))) {
-        mask = Lc->mask[(size_t)w.brick * BN + n];
+      // a wavefront with any special lane pulls every lane through pull_links (plain
+      // lanes have an empty mask there), so it runs one pull instead of two
+      const bool special = !plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW));
+      if (!plain && __builtin_amdgcn_ballot_w64(special) != 0) {
+        mask = special ? Lc->mask[(size_t)w.brick * BN + n] : 0u;
         uint32_t mid[9], side[9];
         bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z, mid, side);
         const BulkLane<D> bl(x, y, z);
