@@ -18,6 +18,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import json
 import os
 import sys
@@ -222,6 +223,7 @@ def cpu_baseline(sp, fe_updates, steps):
 
 
 def main():
+    faulthandler.enable()  # a fatal signal prints the Python stack of every thread
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
