@@ -117,7 +117,7 @@ def fine_equiv_updates(lat, sp):
     return sum(lat.level_info(l)[1] * (1 << l) for l in range(sp.levels))
 
 
-def run_gpu(sp, storage, steps, warmup, tune):
+def run_gpu(sp, storage, steps, warmup, tune, launch=None):
     import torch
 
     from paper_1608_06915_amd import elbm
@@ -131,7 +131,9 @@ def run_gpu(sp, storage, steps, warmup, tune):
         lo, n = lat.level_box(l)
         rho, u, nz = sp.init(l, lo, n)
         lat.init(l, rho, u, nz)
-    if tune:
+    if launch:
+        lat.set_launch(**launch)
+    elif tune:
         lat.tune(os.environ.get("ELBM_TUNE_CACHE"), steps=3)
     print("bench: %s launch %s" % (storage, lat.get_launch()), file=sys.stderr, flush=True)
     lat.advance(warmup)
@@ -234,6 +236,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
+    ap.add_argument("--launch", default=None,
+                    help='fixed launch configuration as JSON, e.g. {"threads": 128} (skips the autotuner)')
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-workload", default="cylinder2d")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -264,7 +268,9 @@ def main():
     sp, desc = workload(args.workload)
     print("bench: workload=%s storage=%s steps=%d warmup=%d" % (args.workload, args.storage, args.steps,
                                                                 args.warmup), file=sys.stderr, flush=True)
-    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, not args.no_tune)
+    launch = json.loads(args.launch) if args.launch else None
+    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, not args.no_tune,
+                                                    launch)
     fe = fine_equiv_updates(lat, sp)
     value = fe * args.steps / (ms / 1e3) / 1e6
     counts = mode_counts(lat, sp)
