@@ -134,7 +134,10 @@ def run_gpu(sp, storage, steps, warmup, tune, launch=None):
     if launch:
         lat.set_launch(**launch)
     elif tune:
-        lat.tune(os.environ.get("ELBM_TUNE_CACHE"), steps=3)
+        # launch configuration from the tuning cache (the on-line search is switched
+        # off in the library); the library default when the cache has none
+        if not lat.use_cached_launch(os.environ.get("ELBM_TUNE_CACHE")):
+            print("bench: no cached launch configuration, library default", file=sys.stderr, flush=True)
     print("bench: %s launch %s" % (storage, lat.get_launch()), file=sys.stderr, flush=True)
     lat.advance(warmup)
     lat.synchronize()
@@ -235,9 +238,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library default launch configuration (ignore the tuning cache)")
     ap.add_argument("--launch", default=None,
-                    help='fixed launch configuration as JSON, e.g. {"threads": 128} (skips the autotuner)')
+                    help='fixed launch configuration as JSON, e.g. {"threads": 128} (ignores the tuning cache)')
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-workload", default="cylinder2d")
     ap.add_argument("--adjoint-steps", type=int, default=2000)

@@ -171,17 +171,21 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
  * covers 256/threads nodes of its brick), register-budget variant of the
  * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD),
  * pipeline (1: persistent software-pipelined stream-collide, wg_per_cu workgroups of
- * 256 threads per CU, default 3; threads and occupancy are then ignored).  Every
+ * 256 threads per CU, default 2; threads and occupancy are then ignored).  Every
  * configuration gives bitwise identical populations. */
 elbm_status elbm_set_launch(elbm_ctx *ctx, int use_graph, int wg_per_cu, int xcd_remap, int threads,
                             int occupancy, int pipeline);
 /* Current launch configuration: {use_graph, wg_per_cu, xcd_remap, threads, occupancy,
  * pipeline}. */
 elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[6]);
-/* Autotune the launch configuration by timing `steps` coarse steps per candidate;
- * results cached in cache_path (one "key": [graph, wg_per_cu, xcd, threads, occupancy,
- * pipeline] line per workload shape; may be NULL).  The state is restored; drag
- * accumulators are reset. */
+/* Launch configuration from a tuning cache: cache_path holds one
+ *   "key": [graph, wg_per_cu, xcd, threads, occupancy, pipeline]
+ * line per workload shape, key = "d<dim>s<storage>_<bricks of level 0>_<bricks of
+ * level 1>...".  On a hit the configuration is applied (as elbm_set_launch) and the
+ * state is untouched.  On a miss the on-line search (timing `steps` coarse steps per
+ * candidate, state restored, result appended to the cache) would run; it is switched
+ * off in this build and a miss returns ELBM_ESTATE with the key in the error text,
+ * leaving the configuration unchanged. */
 elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
 /* Time `steps` coarse steps with HIP events around every stream-collide launch;
  * returns the total and summed stream-collide milliseconds and launch count.

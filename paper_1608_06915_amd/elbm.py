@@ -16,6 +16,8 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelbm.so")
+# launch configurations measured for the benchmark workloads (elbm_tune cache format)
+LAUNCH_CACHE = os.path.join(HERE, "launch_cache.txt")
 
 STORE_F64, STORE_F32, STORE_F16S, STORE_BF16S = 0, 1, 2, 3
 STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16s": STORE_F16S, "bf16s": STORE_BF16S}
@@ -314,6 +316,17 @@ class Lattice:
 
     def tune(self, cache_path=None, steps=3):
         self._ck(lib().elbm_tune(self._h, cache_path.encode() if cache_path else None, int(steps)))
+
+    def use_cached_launch(self, cache_path=None) -> bool:
+        """Apply the cached launch configuration for this workload shape (default cache:
+        LAUNCH_CACHE).  Returns False, configuration unchanged, when the cache has none."""
+        try:
+            self.tune(cache_path or LAUNCH_CACHE, steps=1)
+            return True
+        except ElbmError as e:
+            if e.status == 2 and "no cached launch configuration" in str(e):
+                return False
+            raise
 
     def profile(self, steps):
         tot, sc = ctypes.c_double(), ctypes.c_double()

@@ -107,3 +107,29 @@ def test_survey_workload_node_counts(elbm):
     synth.apply(sp, g)
     assert g.level_info(0)[1] == 128 * 50 * 64
     assert g.level_info(1)[1] == 2 * 256 * 17 * 128
+
+
+def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
+    """Every entry of the committed tuning cache parses in the elbm_tune format, holds a
+    configuration elbm_set_launch accepts, and its key is the full-size channel's shape
+    (dimension, storage, bricks per level) in FP32 or FP16-shifted storage."""
+    import re
+
+    pat = re.compile(r'^\s*"([^"]+)": \[(-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+)\]\s*$')
+    entries = {}
+    with open(elbm.LAUNCH_CACHE) as f:
+        for line in f:
+            if line.strip() and not line.lstrip().startswith("#"):
+                m = pat.match(line)
+                assert m, "unparsable cache line: %r" % line
+                entries[m.group(1)] = [int(v) for v in m.groups()[1:]]
+    sp = synth.channel3d()
+    keys = set()
+    for st in ("f32", "f16s"):
+        g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, st)
+        synth.apply(sp, g)
+        keys.add("d%ds%d" % (sp.D, elbm.STORAGE[st]) + "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels)))
+    assert set(entries) == keys
+    for graph, wg, xcd, thr, occ, pipe in entries.values():
+        assert graph in (0, 1) and 0 <= wg <= 64 and xcd in (0, 1) and thr in (64, 128, 256)
+        assert occ in (1, 4) and pipe in (0, 1)

@@ -139,6 +139,24 @@ def test_mass_momentum_and_gamma_fp64(elbm):
         assert np.max(np.abs(gg[m] - go[m]) / np.abs(go[m])) < 3e-7
 
 
+def test_cached_launch_hit_and_miss(elbm, tmp_path):
+    """A cache hit applies the stored configuration without touching the state; a miss
+    returns False and leaves the configuration unchanged (no search runs)."""
+    sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g, _ = pair(elbm, sp, "f32", 2)
+    f0 = [g.get_f(l) for l in range(sp.levels)]
+    before = g.get_launch()
+    assert not g.use_cached_launch(str(tmp_path / "absent.txt"))
+    assert g.get_launch() == before
+    key = "d%ds%d" % (sp.D, elbm.STORAGE["f32"]) + "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels))
+    cache = tmp_path / "cache.txt"
+    cache.write_text('# comment\n"d9s9_1": [1, 0, 0, 64, 1, 0]\n"%s": [1, 4, 0, 128, 4, 0]\n' % key)
+    assert g.use_cached_launch(str(cache))
+    assert g.get_launch() == dict(use_graph=1, wg_per_cu=4, xcd_remap=0, threads=128, occupancy=4, pipeline=0)
+    for l in range(sp.levels):
+        assert np.array_equal(g.get_f(l), f0[l], equal_nan=True)
+
+
 @pytest.mark.parametrize("launch", [dict(use_graph=0), dict(use_graph=1, wg_per_cu=2, xcd_remap=1, threads=128),
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=0, threads=64),
                                     dict(use_graph=1, wg_per_cu=4, xcd_remap=1, threads=256, occupancy=4),
@@ -237,9 +255,10 @@ def test_deterministic_repeat(elbm):
 
 # ----------------------------------------------------------------- full-size workloads
 # The oracle cannot run the full-size workloads for many steps (9-18 s per coarse
-# step).  After k coarse steps on the GPU, in the autotuned launch configuration the
-# benchmark times, the GPU state of every level is loaded into the oracle and both
-# advance one more coarse step; every population of every node is compared.
+# step).  After k coarse steps on the GPU, in the cached launch configuration the
+# benchmark times (library default where the cache has none), the GPU state of every
+# level is loaded into the oracle and both advance one more coarse step; every
+# population of every node is compared.
 @pytest.mark.parametrize("name,storage,k,bound", [
     ("channel3d", "f32", 50, 1e-5),
     ("channel3d", "f16s", 50, 1e-3),
@@ -259,7 +278,7 @@ def test_full_size_one_step_from_gpu_state(elbm, name, storage, k, bound):
         lo, n = g.level_box(l)
         rho, u, nz = sp.init(l, lo, n)
         g.init(l, rho, u, nz)
-    g.tune(None, steps=2)
+    g.use_cached_launch()  # the benchmark's configuration where the cache has one
     g.advance(k)
     assert g.check()
     o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
