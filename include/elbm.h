@@ -167,7 +167,8 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
 
 /* Launch configuration: use_graph (1: one graph per coarse step), workgroups per CU
  * for the persistent stream-collide grid (0: one workgroup per brick), XCD-aware
- * brick-to-workgroup mapping, threads per workgroup (64, 128 or 256; each thread
+ * brick-to-workgroup mapping (0: none; 1: one contiguous range of bricks per XCD;
+ * B in 2..4096: runs of B consecutive bricks per XCD, dealt round-robin), threads per workgroup (64, 128 or 256; each thread
  * covers 256/threads nodes of its brick), register-budget variant of the
  * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD),
  * pipeline (1: persistent software-pipelined stream-collide, wg_per_cu workgroups of

@@ -108,7 +108,7 @@ struct elbm_ctx {
   std::vector<CTile> tiles_all;
   std::vector<int32_t> tile_rows_all;
   std::vector<StencilEntry> sten, tsten_all;
-  int lds_rows = 1, lds_ents = 1;
+  int lds_rows = 1, lds_ents = 1, lds_items = 1;
   int stage_cols = 0;
   bool finalized = false, bound = false;
   std::string err;
@@ -798,8 +798,9 @@ elbm_status build_pairs(elbm_ctx *c) {
           const CItem &it = its[k];
           int add = 0;
           for (int e = it.a; e < it.a + it.b; ++e) add += local.count(c->sten[e].slot) ? 0 : 1;
-          // close the tile (the same brick continues) when its rows or entries exceed LDS
-          if ((t.npt + add > maxr || t.ne + it.b > maxe) && t.nitem > 0) break;
+          // close the tile (the same brick continues) when its rows, entries or nodes
+          // (whose sums reuse the row area) exceed LDS
+          if ((t.npt + add > maxr || t.ne + it.b > maxe || t.nitem + 1 > maxr) && t.nitem > 0) break;
           t.ne += it.b;
           CItem ti = it;
           ti.a = (int32_t)P.tsten.size();
@@ -824,6 +825,7 @@ elbm_status build_pairs(elbm_ctx *c) {
         }
         c->lds_rows = std::max(c->lds_rows, (int)t.npt);
         c->lds_ents = std::max(c->lds_ents, (int)t.ne);
+        c->lds_items = std::max(c->lds_items, (int)t.nitem);
         P.tiles.push_back(t);
       }
     }
@@ -1078,7 +1080,7 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
       a.dst[l] = dst[l];
     }
     a.flags = flags;
-    a.pad = 0;
+    a.lds_items = c->lds_items;
     LCK(c, launch_couple(c->D, c->storage, a, cs));
   }
   SCArgs s;
@@ -1944,9 +1946,10 @@ elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_r
   if (occupancy != 1 && occupancy != 4) FAIL(c, ELBM_EINVAL, "occupancy variant must be 1 or 4");
   if (threads != 64 && threads != 128 && threads != 256) FAIL(c, ELBM_EINVAL, "threads must be 64, 128 or 256");
   if (wg_per_cu < 0 || wg_per_cu > 64) FAIL(c, ELBM_EINVAL, "wg_per_cu out of range");
+  if (xcd_remap < 0 || xcd_remap > 4096) FAIL(c, ELBM_EINVAL, "xcd_remap out of range");
   c->use_graph = use_graph != 0;
   c->wg_per_cu = wg_per_cu;
-  c->xcd_remap = xcd_remap != 0;
+  c->xcd_remap = xcd_remap;
   c->threads = threads;
   c->occ = occupancy;
   c->pipe = pipeline != 0;

@@ -107,7 +107,7 @@ enum { FL_DRAG = 1, FL_GAMMA = 2 };
 struct SCArgs {
   const ItemRec *items;
   int32_t n_items;
-  int32_t remap;  // XCD-aware item mapping
+  int32_t remap;  // XCD-aware item mapping (0 identity, 1 contiguous ranges, B >= 2 runs of B items)
   int32_t flags;  // FL_DRAG: accumulate momentum exchange, FL_GAMMA: write gamma
   int32_t pad;
   const LevelStatic *lev;
@@ -141,8 +141,8 @@ struct CoupleArgs {
   const PairStatic *pairs;
   void *src[MAXL];
   void *dst[MAXL];
-  int32_t flags;  // FL_GAMMA: write gamma
-  int32_t pad;
+  int32_t flags;      // FL_GAMMA: write gamma
+  int32_t lds_items;  // most fine interface nodes in one tile (the row area also holds their sums)
 };
 
 // ---------------------------------------------------------------- discrete adjoint

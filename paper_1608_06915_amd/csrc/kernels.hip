@@ -18,7 +18,9 @@ namespace elbm {
 // ---------------------------------------------------------------- stream-collide
 // OCC: minimum waves per SIMD requested from the register allocator (1: no cap,
 // 4: at most 128 VGPRs); both variants are built and the launch configuration picks one.
-template <int D, int ST, int OCC>
+// TWO: plain bricks take two nodes per thread (launched with BN/2 threads); built
+// apart from the one-node kernel, whose register count it would otherwise set.
+template <int D, int ST, int OCC, bool TWO>
 __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   using C = Codec<ST>;
   using S = typename C::S;
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   constexpr int Q = nq<D>();
   __shared__ double s_red[3][8];
   const int G = gridDim.x;
-  const int me = (a.remap && (G & 7) == 0) ? xcd_perm(blockIdx.x, G) : blockIdx.x;
+  const int me = xcd_item(blockIdx.x, G, a.remap);
   for (int base = 0; base < a.n_items; base += G) {
     const int idx = base + me;
     if (idx >= a.n_items) break;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
       }
       __syncthreads();
     }
-    if (plain && blockDim.x == BN / 2) {
+    if (TWO && plain) {
       // plain brick, two nodes per thread: both nodes' loads are issued before either
       // collision, doubling the bytes in flight per wavefront
       const int n0 = threadIdx.x, n1 = n0 + BN / 2;
@@ -189,7 +191,7 @@ template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCA
   constexpr int Q = nq<D>();
   __shared__ ItemRec srec[PIPE_RECS];
   const int G = gridDim.x;
-  const int me = (a.remap && (G & 7) == 0) ? xcd_perm(blockIdx.x, G) : blockIdx.x;
+  const int me = xcd_item(blockIdx.x, G, a.remap);
   if (me >= a.n_items) return;
   const int cnt = (a.n_items - me + G - 1) / G;
   const int n = threadIdx.x;
@@ -302,9 +304,13 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherA
 // fine post-stream state with f^neq brought to coarse scale.  Both then collide with
 // their own level's parameters (Sec. III.C steps 3-5).
 // Fine interface nodes are processed per tile (one workgroup per fine brick): the
-// staged rows its stencils use are copied to LDS once, then every node accumulates
-// its tensor stencil from LDS.  Ring nodes are handled by the trailing workgroups.
+// staged rows its stencils use are copied to LDS once; then every (node, 4-value
+// column) pair is one lane's task, accumulating that column over the node's stencil
+// (the lanes of a node share its entry count, so a wavefront runs no idle
+// iterations); the sums go back to LDS over the rows and one lane per node collides.
+// Ring nodes are handled by the trailing workgroups.
 constexpr int COUPLE_LDS_BYTES = 48 * 1024;
+constexpr int COUPLE_THREADS = 256;
 template <int D, typename T> __host__ __device__ constexpr int couple_rows() {
   return COUPLE_LDS_BYTES / (lds_stride<D, T>() * (int)sizeof(T));
 }
@@ -324,47 +330,82 @@ template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &
   if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
 }
 
-template <int D, int ST> __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
+template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F64 ? 2 : 4) void k_couple(CoupleArgs a) {
   using C = Codec<ST>;
   using T = typename C::T;
   using V = typename V4<T>::type;
   constexpr int Q = nq<D>();
   constexpr int SW = stage_width<D>();
+  constexpr int NV = SW / 4;  // 4-element columns of a staged row
+  constexpr int SL = lds_stride<D, T>();
+  constexpr int NT = COUPLE_THREADS;
+  constexpr int TPT = (BN * NV + NT - 1) / NT;  // column tasks per lane (a tile holds at most BN nodes)
   extern __shared__ __align__(16) unsigned char couple_lds[];
   T *rows = (T *)couple_lds;
   if ((int)blockIdx.x < a.n_tiles) {
     const CTile t = a.tiles[blockIdx.x];
     const V *stage = (const V *)a.stage;
     // entries packed to 4 bytes: tile-local row (16 bits) and the weight in FP16 (the
-    // weights are products of -1/16, 9/16 and 1: exact in FP16)
-    constexpr int SL = lds_stride<D, T>();
-    uint32_t *ents = (uint32_t *)(rows + (size_t)a.lds_rows * SL);
-    for (int k = threadIdx.x; k < t.npt * (SW / 4); k += blockDim.x) {
-      const int r = k / (SW / 4), q = k - r * (SW / 4);
-      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
+    // weights are products of -1/16, 9/16 and 1: exact in FP16); the row area also
+    // holds the per-node sums of the last phase
+    const int rcap = a.lds_rows > a.lds_items ? a.lds_rows : a.lds_items;
+    uint32_t *ents = (uint32_t *)(rows + (size_t)rcap * SL);
+    for (int k = threadIdx.x; k < t.npt * NV; k += NT) {
+      const int r = k / NV, q = k - r * NV;
+      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * NV + q];
     }
-    for (int k = threadIdx.x; k < t.ne; k += blockDim.x) {
+    for (int k = threadIdx.x; k < t.ne; k += NT) {
       const StencilEntry s = a.sten[t.e0 + k];
       ents[k] = (uint32_t)s.slot | ((uint32_t)__half_as_ushort(__float2half_rn(s.w)) << 16);
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < t.nitem; it += blockDim.x) {
+    const int ntask = t.nitem * NV;
+    T ax[TPT], ay[TPT], az[TPT], aw[TPT];
+#pragma unroll
+    for (int p = 0; p < TPT; ++p) {
+      ax[p] = ay[p] = az[p] = aw[p] = T(0);
+      const int k = p * NT + (int)threadIdx.x;
+      if (k < ntask) {
+        const int node = k / NV, col = k - node * NV;
+        const CItem c = a.items[t.item0 + node];
+        const int e1 = c.a - t.e0 + c.b;
+        for (int e = c.a - t.e0; e < e1; ++e) {
+          const uint32_t s = ents[e];
+          const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
+          const V r = ((const V *)(rows + (s & 0xffffu) * SL))[col];
+          ax[p] = fma(w, r.x, ax[p]);
+          ay[p] = fma(w, r.y, ay[p]);
+          az[p] = fma(w, r.z, az[p]);
+          aw[p] = fma(w, r.w, aw[p]);
+        }
+      }
+    }
+    __syncthreads();  // the staged rows are no longer read
+#pragma unroll
+    for (int p = 0; p < TPT; ++p) {
+      const int k = p * NT + (int)threadIdx.x;
+      if (k < ntask) {
+        const int node = k / NV, col = k - node * NV;
+        V v;
+        v.x = ax[p];
+        v.y = ay[p];
+        v.z = az[p];
+        v.w = aw[p];
+        ((V *)rows)[node * (SL / 4) + col] = v;
+      }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < t.nitem; it += NT) {
       const CItem c = a.items[t.item0 + it];
       T acc[SW];
+      const V *row = (const V *)(rows + it * SL);
 #pragma unroll
-      for (int v = 0; v < SW; ++v) acc[v] = 0;
-      for (int e = c.a - t.e0; e < c.a - t.e0 + c.b; ++e) {
-        const uint32_t s = ents[e];
-        const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
-        const V *row = (const V *)(rows + (s & 0xffffu) * SL);
-#pragma unroll
-        for (int v = 0; v < SW / 4; ++v) {
-          const V r = row[v];
-          acc[4 * v + 0] = fma(w, r.x, acc[4 * v + 0]);
-          acc[4 * v + 1] = fma(w, r.y, acc[4 * v + 1]);
-          acc[4 * v + 2] = fma(w, r.z, acc[4 * v + 2]);
-          acc[4 * v + 3] = fma(w, r.w, acc[4 * v + 3]);
-        }
+      for (int v = 0; v < NV; ++v) {
+        const V r = row[v];
+        acc[4 * v + 0] = r.x;
+        acc[4 * v + 1] = r.y;
+        acc[4 * v + 2] = r.z;
+        acc[4 * v + 3] = r.w;
       }
       T u[3] = {acc[1], acc[2], D == 3 ? acc[3] : T(0)};
       T q[Q], h[Q];
@@ -620,10 +661,15 @@ int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *s
     ELBM_DISPATCH(D, st, (k_sc_pipe<DD, SS><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
     return ck();
   }
-  if (cfg.occ >= 4)
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+  const bool two = thr == BN / 2;
+  if (cfg.occ >= 4 && two)
+    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, true><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+  else if (cfg.occ >= 4)
+    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, false><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+  else if (two)
+    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 1, true><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
   else
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 1><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 1, false><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
   return ck();
 }
 
@@ -654,11 +700,12 @@ int couple_max_rows(int D, int st) {
 int launch_couple(int D, int st, const CoupleArgs &a, void *stream) {
   // one workgroup of two wavefronts per tile (a tile holds one or two brick layers of
   // interface nodes); LDS sized to the largest tile, so several tiles share a CU
-  const int ring_blocks = (a.n_ring + 127) / 128;
+  const int ring_blocks = (a.n_ring + COUPLE_THREADS - 1) / COUPLE_THREADS;
   const int grid = a.n_tiles + ring_blocks;
   if (grid <= 0) return 0;
-  const size_t lds = (size_t)a.lds_rows * couple_lds_stride(D, st) * (st == ST_F64 ? 8 : 4) + (size_t)a.lds_ents * 4;
-  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, 128, lds, (hipStream_t)stream>>>(a)));
+  const int rcap = a.lds_rows > a.lds_items ? a.lds_rows : a.lds_items;
+  const size_t lds = (size_t)rcap * couple_lds_stride(D, st) * (st == ST_F64 ? 8 : 4) + (size_t)a.lds_ents * 4;
+  ELBM_DISPATCH(D, st, (k_couple<DD, SS><<<grid, COUPLE_THREADS, lds, (hipStream_t)stream>>>(a)));
   return ck();
 }
 

@@ -457,6 +457,7 @@ __device__ inline void pull_special(const char *__restrict__ srcb, OFF boff, con
 
 template <int D> struct BulkLane {
   bool xlo, xhi, ylo, yhi;  // per lane: on the low/high x (y) face of the brick
+  uint32_t mxlo, mxhi, mylo, myhi;  // the same as all-ones / zero masks
   int lx[3], ly[3];         // local x, y of the source for c = +1, 0, -1 (index 1 - c)
   int lz[3];                // local z part (uniform)
   bool zlo, zhi;            // uniform
@@ -466,6 +467,10 @@ template <int D> struct BulkLane {
     xhi = x == Bk::BX - 1;
     ylo = y == 0;
     yhi = y == Bk::BY - 1;
+    mxlo = 0u - (uint32_t)xlo;
+    mxhi = 0u - (uint32_t)xhi;
+    mylo = 0u - (uint32_t)ylo;
+    myhi = 0u - (uint32_t)yhi;
     static_for<0, 3>([&](auto K) {
       constexpr int k = decltype(K)::value;
       lx[k] = (x - 1 + k) & (Bk::BX - 1);
@@ -480,8 +485,42 @@ template <int D> struct BulkLane {
 // Bulk pull.  mid[k]: byte offset of the neighbour brick at displacement code 9 + k
 // (same z-layer of bricks), side[k]: the brick layer below (z on the low brick face)
 // or above (z on the high face) -- z is uniform over a wavefront, so one side layer
-// suffices.  Offsets are wave-uniform scalars; lanes on x/y brick faces select
-// among them per population.
+// suffices.  Offsets are wave-uniform scalars.  A lane on an x (y) brick face takes
+// the neighbour brick for that axis; the choice is formed branch-free as
+//   base = O + (mx & dX) + (my & dY) + (mx & my & dXY)
+// with the lane's face masks and scalar differences of the candidate offsets (a
+// select between two scalars is not one vector instruction here, and as a select it
+// compiles to divergent branches).
+template <int D, int I>
+__device__ inline uint32_t bulk_base(const uint32_t (&mid)[9], const uint32_t (&side)[9], const BulkLane<D> &b) {
+  constexpr int cx = cxo(I), cy = cyo(I), cz = czo<D>(I);
+  // candidate brick offsets (wave-uniform): x index kx, y index ky into the 3x3 layer;
+  // interior lanes use (1, 1)
+  auto U = [&](int kx, int ky) -> uint32_t {
+    const int k = kx + 3 * ky;
+    uint32_t v = mid[k];
+    if constexpr (cz == 1) v = b.zlo ? side[k] : mid[k];
+    if constexpr (cz == -1) v = b.zhi ? side[k] : mid[k];
+    return __builtin_amdgcn_readfirstlane(v);
+  };
+  constexpr int ex = cx == 1 ? 0 : 2, ey = cy == 1 ? 0 : 2;  // edge candidates
+  const uint32_t o11 = U(1, 1);
+  uint32_t base = o11;
+  if constexpr (cx != 0) {
+    const uint32_t mx = cx == 1 ? b.mxlo : b.mxhi;
+    base += mx & (U(ex, 1) - o11);
+    if constexpr (cy != 0) {
+      const uint32_t my = cy == 1 ? b.mylo : b.myhi;
+      base += my & (U(1, ey) - o11);
+      base += (mx & my) & (U(ex, ey) - U(ex, 1) - U(1, ey) + o11);
+    }
+  } else if constexpr (cy != 0) {
+    const uint32_t my = cy == 1 ? b.mylo : b.myhi;
+    base += my & (U(1, ey) - o11);
+  }
+  return base;
+}
+
 template <int D, int ST, typename LD>
 __device__ inline void pull_bulk_with(const uint32_t (&mid)[9], const uint32_t (&side)[9], const BulkLane<D> &b,
                                       LD ld) {
@@ -489,24 +528,7 @@ __device__ inline void pull_bulk_with(const uint32_t (&mid)[9], const uint32_t (
   static_for<0, nq<D>()>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
-    // the candidates are wave-uniform; readfirstlane keeps them scalar values so the
-    // per-lane choice stays a register select (not an indexed load)
-    auto U = [&](int k) -> uint32_t {
-      uint32_t v = mid[k];
-      if constexpr (cz == 1) v = b.zlo ? side[k] : mid[k];
-      if constexpr (cz == -1) v = b.zhi ? side[k] : mid[k];
-      return __builtin_amdgcn_readfirstlane(v);
-    };
-    auto Ox = [&](auto BY) -> uint32_t {
-      constexpr int by = decltype(BY)::value;
-      if constexpr (cx == 1) return b.xlo ? U(0 + 3 * by) : U(1 + 3 * by);
-      else if constexpr (cx == -1) return b.xhi ? U(2 + 3 * by) : U(1 + 3 * by);
-      else return U(1 + 3 * by);
-    };
-    uint32_t base;
-    if constexpr (cy == 1) base = b.ylo ? Ox(Ic<0>()) : Ox(Ic<1>());
-    else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
-    else base = Ox(Ic<1>());
+    const uint32_t base = bulk_base<D, i>(mid, side, b);
     const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
     ld(i, base + (uint32_t)(loc * (int)sizeof(S)), (uint32_t)(i * BN * (int)sizeof(S)));
   });
@@ -551,22 +573,7 @@ __device__ inline void pull_links_with(const uint32_t (&md)[9], const uint32_t (
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
-    auto U = [&](int k) -> uint32_t {
-      uint32_t v = md[k];
-      if constexpr (cz == 1) v = b.zlo ? sd[k] : md[k];
-      if constexpr (cz == -1) v = b.zhi ? sd[k] : md[k];
-      return __builtin_amdgcn_readfirstlane(v);
-    };
-    auto Ox = [&](auto BY) -> uint32_t {
-      constexpr int by = decltype(BY)::value;
-      if constexpr (cx == 1) return b.xlo ? U(0 + 3 * by) : U(1 + 3 * by);
-      else if constexpr (cx == -1) return b.xhi ? U(2 + 3 * by) : U(1 + 3 * by);
-      else return U(1 + 3 * by);
-    };
-    uint32_t base;
-    if constexpr (cy == 1) base = b.ylo ? Ox(Ic<0>()) : Ox(Ic<1>());
-    else if constexpr (cy == -1) base = b.yhi ? Ox(Ic<2>()) : Ox(Ic<1>());
-    else base = Ox(Ic<1>());
+    const uint32_t base = bulk_base<D, i>(md, sd, b);
     const int loc = b.lx[1 - cx] + b.ly[1 - cy] + b.lz[1 - cz];
     const bool hit = (mask >> i) & 1u;
     uint32_t v = base + (uint32_t)((i * BN + loc) * (int)sizeof(S));
@@ -622,9 +629,23 @@ template <int D> __device__ inline void node_xyz(int n, int &x, int &y, int &z) 
   z = D == 3 ? (n >> (Bk::LX + Bk::LY)) : 0;
 }
 
-__device__ inline int xcd_perm(int b, int G) {
-  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range
-  return (b & 7) * (G >> 3) + (b >> 3);
+// Item of workgroup b in a grid of G.  The hardware deals workgroups round-robin to
+// the 8 XCDs (b & 7), each with its own L2.  mode 0: identity; mode 1: each XCD gets
+// one contiguous range of G/8 items (G a multiple of 8, else identity); mode B >= 2:
+// runs of B consecutive items go to one XCD and the runs are dealt round-robin, so
+// bricks that share halo lines (consecutive bricks are x-neighbours) meet in one L2
+// while every XCD still sweeps the whole item range; workgroups past the last whole
+// round of 8 runs keep their own index.  Every mode is a bijection of [0, G).
+__device__ inline int xcd_item(int b, int G, int mode) {
+  if (mode == 1) return (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
+  if (mode >= 2) {
+    const int round = 8 * mode;
+    if (b < G / round * round) {
+      const int l = b >> 3;  // position of b among its XCD's workgroups
+      return ((l / mode) * 8 + (b & 7)) * mode + l % mode;
+    }
+  }
+  return b;
 }
 
 

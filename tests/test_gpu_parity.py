@@ -161,8 +161,11 @@ def test_cached_launch_hit_and_miss(elbm, tmp_path):
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=0, threads=64),
                                     dict(use_graph=1, wg_per_cu=4, xcd_remap=1, threads=256, occupancy=4),
                                     dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=1),
-                                    dict(use_graph=0, wg_per_cu=3, xcd_remap=0, pipeline=1)],
-                         ids=["eager", "persistent-xcd", "oneperbrick", "regcap", "pipelined", "pipelined-eager"])
+                                    dict(use_graph=0, wg_per_cu=3, xcd_remap=0, pipeline=1),
+                                    dict(use_graph=1, wg_per_cu=0, xcd_remap=2, threads=128),
+                                    dict(use_graph=1, wg_per_cu=2, xcd_remap=3, pipeline=1)],
+                         ids=["eager", "persistent-xcd", "oneperbrick", "regcap", "pipelined", "pipelined-eager",
+                              "xcd-runs", "pipelined-xcd-runs"])
 def test_launch_configurations_bitwise_equal(elbm, launch):
     sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
     g0, o = pair(elbm, sp, "f32", 6)
