@@ -171,9 +171,12 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
  * B in 2..4096: runs of B consecutive bricks per XCD, dealt round-robin), threads per workgroup (64, 128 or 256; each thread
  * covers 256/threads nodes of its brick), register-budget variant of the
  * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD),
- * pipeline (1: persistent software-pipelined stream-collide, wg_per_cu workgroups of
- * 256 threads per CU, default 2; threads and occupancy are then ignored).  Every
- * configuration gives bitwise identical populations. */
+ * pipeline (plain bricks -- every node fluid with bulk links only -- in a kernel of
+ * their own and the other bricks in the general kernel with 256 threads: 1: persistent
+ * software-pipelined, wg_per_cu workgroups per CU, default 2; 2: one node per thread
+ * within 128 registers, one workgroup per brick unless wg_per_cu is set; threads and
+ * occupancy then do not apply to the plain bricks).  Every configuration gives
+ * bitwise identical populations. */
 elbm_status elbm_set_launch(elbm_ctx *ctx, int use_graph, int wg_per_cu, int xcd_remap, int threads,
                             int occupancy, int pipeline);
 /* Current launch configuration: {use_graph, wg_per_cu, xcd_remap, threads, occupancy,

@@ -84,7 +84,7 @@ struct Pair {
 struct Tick {
   int lmin;
   size_t sc_off, sc_n, gp_off, gp_n, tile_off, tile_n, ring_off, ring_n;
-  size_t sc_plain;  // the first sc_plain items of the tick are plain bricks
+  size_t sc_plain;  // the last sc_plain items of the tick are plain bricks
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -117,8 +117,8 @@ struct elbm_ctx {
          o_trows = 0, o_sten = 0, o_stage = 0, o_redit = 0, o_part = 0, o_res = 0, o_tmp = 0;
   size_t tmp_bytes = 0;
   char *ws = nullptr;
-  hipStream_t stream = nullptr, side = nullptr, cap = nullptr;
-  hipEvent_t ev_fork[64], ev_join[64];
+  hipStream_t stream = nullptr, side = nullptr, cap = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork[64], ev_join[64], ev_fork2[64], ev_join2[64];
   int n_events = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool graph_valid = false;
@@ -913,10 +913,12 @@ void build_schedule(elbm_ctx *c) {
       c->sc_all.insert(c->sc_all.end(), v.begin(), v.end());
     }
     tk.sc_n = c->sc_all.size() - tk.sc_off;
-    // plain bricks first (the pipelined stream-collide takes them)
+    // plain bricks last: in one launch the costlier bricks (walls, interface layers,
+    // boundaries) start first instead of forming the tail; the split modes take the
+    // plain suffix
     auto mid = std::stable_partition(c->sc_all.begin() + tk.sc_off, c->sc_all.end(),
-                                     [](const WorkItem &w) { return (w.flags & WI_PLAIN) != 0; });
-    tk.sc_plain = (size_t)(mid - (c->sc_all.begin() + tk.sc_off));
+                                     [](const WorkItem &w) { return (w.flags & WI_PLAIN) == 0; });
+    tk.sc_plain = (size_t)(c->sc_all.end() - mid);
     const int p0 = std::min(lmin, pL);
     tk.gp_off = gp_start[p0];
     tk.gp_n = gp_start[pL] - tk.gp_off;
@@ -1099,25 +1101,38 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
   cfg.occ = c->occ;
   cfg.pipe = 0;
   cfg.grid = c->wg_per_cu > 0 ? std::min<int>((int)tk.sc_n, c->wg_per_cu * c->cu_count) : (int)tk.sc_n;
-  // pipelined mode: plain bricks in the persistent pipelined kernel, the others (walls,
-  // interface layers, inlet/outflow, drag) one brick per workgroup
+  // split modes: plain bricks in a plain-only kernel (1: persistent pipelined, 2: one
+  // node per thread within 128 VGPRs), the others (walls, interface layers,
+  // inlet/outflow, drag) in the general kernel, one brick per workgroup
   SCArgs sp = s, sr = s;
   LaunchCfg cp = cfg, cr = cfg;
   const bool split = c->pipe && tk.sc_plain > 0;
   if (split) {
+    sp.items = s.items + (tk.sc_n - tk.sc_plain);
     sp.n_items = (int)tk.sc_plain;
-    cp.pipe = 1;
-    cp.grid = std::min<int>((int)tk.sc_plain, (c->wg_per_cu > 0 ? c->wg_per_cu : 2) * c->cu_count);
-    sr.items = s.items + tk.sc_plain;
+    cp.pipe = c->pipe;
+    if (c->pipe == 1)
+      cp.grid = std::min<int>((int)tk.sc_plain, (c->wg_per_cu > 0 ? c->wg_per_cu : 2) * c->cu_count);
+    else
+      cp.grid = c->wg_per_cu > 0 ? std::min<int>((int)tk.sc_plain, c->wg_per_cu * c->cu_count) : (int)tk.sc_plain;
     sr.n_items = (int)(tk.sc_n - tk.sc_plain);
     cr.grid = sr.n_items;
     cr.occ = 1;
     cr.threads = 256;
   }
   auto run = [&]() -> elbm_status {
-    if (split) {
+    if (split && fork) {
+      // in a graph the two launches are parallel branches (disjoint bricks, same inputs)
+      hipEvent_t f2 = c->ev_fork2[(t - 1) % 64], j2 = c->ev_join2[(t - 1) % 64];
+      HIPCK(c, hipEventRecord(f2, main));
+      HIPCK(c, hipStreamWaitEvent(c->side2, f2, 0));
+      LCK(c, launch_stream_collide(c->D, c->storage, sr, cr, c->side2));
       LCK(c, launch_stream_collide(c->D, c->storage, sp, cp, main));
+      HIPCK(c, hipEventRecord(j2, c->side2));
+      HIPCK(c, hipStreamWaitEvent(main, j2, 0));
+    } else if (split) {
       LCK(c, launch_stream_collide(c->D, c->storage, sr, cr, main));
+      LCK(c, launch_stream_collide(c->D, c->storage, sp, cp, main));
     } else {
       LCK(c, launch_stream_collide(c->D, c->storage, s, cfg, main));
     }
@@ -1472,14 +1487,18 @@ elbm_status elbm_destroy(elbm_ctx *c) {
   // events and streams are released
   if (c->bound) hipStreamSynchronize(c->stream);
   if (c->side) hipStreamSynchronize(c->side);
+  if (c->side2) hipStreamSynchronize(c->side2);
   invalidate_graphs(c);
   for (hipEvent_t e : c->tev) hipEventDestroy(e);
   for (int i = 0; i < c->n_events; ++i) {
     hipEventDestroy(c->ev_fork[i]);
     hipEventDestroy(c->ev_join[i]);
+    hipEventDestroy(c->ev_fork2[i]);
+    hipEventDestroy(c->ev_join2[i]);
   }
   if (c->side) hipStreamDestroy(c->side);
   if (c->cap) hipStreamDestroy(c->cap);
+  if (c->side2) hipStreamDestroy(c->side2);
   delete c;
   return ELBM_OK;
 }
@@ -1675,10 +1694,13 @@ elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
   c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (!c->side) HIPCK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   if (!c->cap) HIPCK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->side2) HIPCK(c, hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
   if (!c->n_events) {
     for (int i = 0; i < 64; ++i) {
       HIPCK(c, hipEventCreateWithFlags(&c->ev_fork[i], hipEventDisableTiming));
       HIPCK(c, hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming));
+      HIPCK(c, hipEventCreateWithFlags(&c->ev_fork2[i], hipEventDisableTiming));
+      HIPCK(c, hipEventCreateWithFlags(&c->ev_join2[i], hipEventDisableTiming));
     }
     c->n_events = 64;
   }
@@ -1946,13 +1968,14 @@ elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_r
   if (occupancy != 1 && occupancy != 4) FAIL(c, ELBM_EINVAL, "occupancy variant must be 1 or 4");
   if (threads != 64 && threads != 128 && threads != 256) FAIL(c, ELBM_EINVAL, "threads must be 64, 128 or 256");
   if (wg_per_cu < 0 || wg_per_cu > 64) FAIL(c, ELBM_EINVAL, "wg_per_cu out of range");
+  if (pipeline < 0 || pipeline > 2) FAIL(c, ELBM_EINVAL, "pipeline must be 0, 1 or 2");
   if (xcd_remap < 0 || xcd_remap > 4096) FAIL(c, ELBM_EINVAL, "xcd_remap out of range");
   c->use_graph = use_graph != 0;
   c->wg_per_cu = wg_per_cu;
   c->xcd_remap = xcd_remap;
   c->threads = threads;
   c->occ = occupancy;
-  c->pipe = pipeline != 0;
+  c->pipe = pipeline;
   invalidate_graphs(c);
   return ELBM_OK;
 }

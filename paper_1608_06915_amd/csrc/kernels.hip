@@ -20,7 +20,9 @@ namespace elbm {
 // 4: at most 128 VGPRs); both variants are built and the launch configuration picks one.
 // TWO: plain bricks take two nodes per thread (launched with BN/2 threads); built
 // apart from the one-node kernel, whose register count it would otherwise set.
-template <int D, int ST, int OCC, bool TWO>
+// PLAIN: every item is a plain brick (the caller launches the plain prefix of a tick's
+// items with it); no code for walls, boundaries or drag, hence fewer registers.
+template <int D, int ST, int OCC, bool TWO, bool PLAIN = false>
 __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   using C = Codec<ST>;
   using S = typename C::S;
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
     WorkItem w;
     w.brick = (int32_t)(uint32_t)wi;
     const int wl = (int)((wi >> 32) & 0xff), wthr = (int)((wi >> 40) & 0xff), wdrag = (int)((wi >> 48) & 0xff);
-    const bool plain = ((wi >> 56) & WI_PLAIN) != 0;
+    const bool plain = PLAIN || ((wi >> 56) & WI_PLAIN) != 0;
     cptr<LevelStatic> Lc = cst(a.lev) + wl;
     cptr<int32_t> nbp = rec->nbr;
     const uint8_t *__restrict__ cls_p = Lc->cls + (size_t)w.brick * BN;
@@ -657,8 +659,12 @@ int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *s
   if (a.n_items <= 0) return 0;
   const int grid = cfg.grid > 0 ? cfg.grid : a.n_items;
   const int thr = cfg.threads > 0 ? cfg.threads : 256;
-  if (cfg.pipe) {  // persistent pipelined variant for plain bricks: one node per thread
+  if (cfg.pipe == 1) {  // persistent pipelined variant for plain bricks: one node per thread
     ELBM_DISPATCH(D, st, (k_sc_pipe<DD, SS><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
+    return ck();
+  }
+  if (cfg.pipe == 2) {  // plain bricks, one node per thread, at most 128 VGPRs
+    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, false, true><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
     return ck();
   }
   const bool two = thr == BN / 2;

@@ -132,4 +132,4 @@ def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
     assert set(entries) == keys
     for graph, wg, xcd, thr, occ, pipe in entries.values():
         assert graph in (0, 1) and 0 <= wg <= 64 and 0 <= xcd <= 4096 and thr in (64, 128, 256)
-        assert occ in (1, 4) and pipe in (0, 1)
+        assert occ in (1, 4) and pipe in (0, 1, 2)

@@ -163,9 +163,11 @@ def test_cached_launch_hit_and_miss(elbm, tmp_path):
                                     dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=1),
                                     dict(use_graph=0, wg_per_cu=3, xcd_remap=0, pipeline=1),
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=2, threads=128),
-                                    dict(use_graph=1, wg_per_cu=2, xcd_remap=3, pipeline=1)],
+                                    dict(use_graph=1, wg_per_cu=2, xcd_remap=3, pipeline=1),
+                                    dict(use_graph=1, wg_per_cu=0, xcd_remap=2, pipeline=2),
+                                    dict(use_graph=0, wg_per_cu=1, xcd_remap=0, pipeline=2)],
                          ids=["eager", "persistent-xcd", "oneperbrick", "regcap", "pipelined", "pipelined-eager",
-                              "xcd-runs", "pipelined-xcd-runs"])
+                              "xcd-runs", "pipelined-xcd-runs", "plain-split", "plain-split-persistent"])
 def test_launch_configurations_bitwise_equal(elbm, launch):
     sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
     g0, o = pair(elbm, sp, "f32", 6)
@@ -197,13 +199,15 @@ def test_sphere_three_level_inlet_outflow_drag_fp32(elbm):
     assert np.allclose(Fg, Fo, rtol=1e-5, atol=2e-6)
 
 
-def test_sphere_pipelined_bitwise_equal_with_drag(elbm):
-    """Special links (inlet, outflow, solid) and the drag reduction in the pipelined
-    stream-collide: same populations and drag as the one-brick-per-workgroup kernel."""
+@pytest.mark.parametrize("pipeline", [1, 2])
+def test_sphere_pipelined_bitwise_equal_with_drag(elbm, pipeline):
+    """Special links (inlet, outflow, solid) and the drag reduction with the plain bricks
+    in a kernel of their own: same populations and drag as the one-brick-per-workgroup
+    kernel."""
     sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
                         centre=(20, 12, 12))
     g0, _ = pair(elbm, sp, "f32", 5)
-    g1, _ = pair(elbm, sp, "f32", 5, launch=dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=1))
+    g1, _ = pair(elbm, sp, "f32", 5, launch=dict(use_graph=1, wg_per_cu=2, xcd_remap=1, pipeline=pipeline))
     for l in range(sp.levels):
         assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
     assert np.array_equal(g0.drag(2)[0], g1.drag(2)[0])
