@@ -165,7 +165,9 @@ elbm_status elbm_drag(elbm_ctx *ctx, int level, double F[3], int64_t *steps, int
 /* Write gamma (Eq. gamma_min_approx) of every collision to a per-node buffer. */
 elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
 
-/* Launch configuration: use_graph (1: one graph per coarse step), workgroups per CU
+/* Launch configuration: use_graph (0: eager launches; 1: one graph per coarse step;
+ * G in 2..64: graphs of G coarse steps, single-step graphs for the remainder of an
+ * elbm_advance), workgroups per CU
  * for the persistent stream-collide grid (0: one workgroup per brick), XCD-aware
  * brick-to-workgroup mapping (0: none; 1: one contiguous range of bricks per XCD;
  * B in 2..4096: runs of B consecutive bricks per XCD, dealt round-robin), threads per workgroup (64, 128 or 256; each thread

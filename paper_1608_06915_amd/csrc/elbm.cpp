@@ -120,7 +120,8 @@ struct elbm_ctx {
   hipStream_t stream = nullptr, side = nullptr, cap = nullptr, side2 = nullptr;
   hipEvent_t ev_fork[64], ev_join[64], ev_fork2[64], ev_join2[64];
   int n_events = 0;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};   // one coarse step, by level-0 parity
+  hipGraphExec_t graphm[2] = {nullptr, nullptr};  // use_graph coarse steps, by level-0 parity
   bool graph_valid = false;
   int parity = 0;  // buffer index of level 0
   int64_t drag_steps[MAXL] = {};
@@ -1028,11 +1029,16 @@ elbm_status upload_static(elbm_ctx *c) {
 }
 
 void invalidate_graphs(elbm_ctx *c) {
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < 2; ++p) {
     if (c->graph[p]) {
       hipGraphExecDestroy(c->graph[p]);
       c->graph[p] = nullptr;
     }
+    if (c->graphm[p]) {
+      hipGraphExecDestroy(c->graphm[p]);
+      c->graphm[p] = nullptr;
+    }
+  }
   c->graph_valid = false;
 }
 
@@ -1181,21 +1187,30 @@ elbm_status enqueue_coarse_step(elbm_ctx *c, int p, hipStream_t main, hipStream_
   return ELBM_OK;
 }
 
+// capture `steps` consecutive coarse steps starting at level-0 parity p
+elbm_status capture_steps(elbm_ctx *c, int p, int steps, hipGraphExec_t *out) {
+  HIPCK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  elbm_status s = ELBM_OK;
+  for (int k = 0; k < steps && !s; ++k) s = enqueue_coarse_step(c, p ^ (k & 1), c->cap, c->side, true);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (s) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return ELBM_OK;
+}
+
 elbm_status build_graphs(elbm_ctx *c) {
   invalidate_graphs(c);
   for (int p = 0; p < 2; ++p) {
-    HIPCK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    elbm_status s = enqueue_coarse_step(c, p, c->cap, c->side, true);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(c->cap, &g);
-    if (s) {
-      if (g) hipGraphDestroy(g);
-      return s;
-    }
-    if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    elbm_status s = capture_steps(c, p, 1, &c->graph[p]);
+    if (!s && c->use_graph > 1) s = capture_steps(c, p, c->use_graph, &c->graphm[p]);
+    if (s) return s;
   }
   c->graph_valid = true;
   return ELBM_OK;
@@ -1820,6 +1835,13 @@ elbm_status elbm_advance(elbm_ctx *c, int n) {
     elbm_status s = build_graphs(c);
     if (s) return s;
   }
+  // whole multi-step graphs first, then single steps
+  const int G = (c->use_graph > 1 && !c->timing) ? c->use_graph : 1;
+  for (; G > 1 && n >= G; n -= G) {
+    HIPCK(c, hipGraphLaunch(c->graphm[c->parity], c->stream));
+    c->parity ^= G & 1;
+    for (int l = 0; l < c->L; ++l) c->drag_steps[l] += (int64_t)G << l;
+  }
   for (int i = 0; i < n; ++i) {
     if (c->use_graph && !c->timing) {
       HIPCK(c, hipGraphLaunch(c->graph[c->parity], c->stream));
@@ -1969,8 +1991,9 @@ elbm_status elbm_set_launch(elbm_ctx *c, int use_graph, int wg_per_cu, int xcd_r
   if (threads != 64 && threads != 128 && threads != 256) FAIL(c, ELBM_EINVAL, "threads must be 64, 128 or 256");
   if (wg_per_cu < 0 || wg_per_cu > 64) FAIL(c, ELBM_EINVAL, "wg_per_cu out of range");
   if (pipeline < 0 || pipeline > 2) FAIL(c, ELBM_EINVAL, "pipeline must be 0, 1 or 2");
+  if (use_graph < 0 || use_graph > 64) FAIL(c, ELBM_EINVAL, "use_graph must be 0..64");
   if (xcd_remap < 0 || xcd_remap > 4096) FAIL(c, ELBM_EINVAL, "xcd_remap out of range");
-  c->use_graph = use_graph != 0;
+  c->use_graph = use_graph;
   c->wg_per_cu = wg_per_cu;
   c->xcd_remap = xcd_remap;
   c->threads = threads;

@@ -131,5 +131,5 @@ def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
         keys.add("d%ds%d" % (sp.D, elbm.STORAGE[st]) + "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels)))
     assert set(entries) == keys
     for graph, wg, xcd, thr, occ, pipe in entries.values():
-        assert graph in (0, 1) and 0 <= wg <= 64 and 0 <= xcd <= 4096 and thr in (64, 128, 256)
+        assert 0 <= graph <= 64 and 0 <= wg <= 64 and 0 <= xcd <= 4096 and thr in (64, 128, 256)
         assert occ in (1, 4) and pipe in (0, 1, 2)

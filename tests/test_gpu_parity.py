@@ -165,9 +165,12 @@ def test_cached_launch_hit_and_miss(elbm, tmp_path):
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=2, threads=128),
                                     dict(use_graph=1, wg_per_cu=2, xcd_remap=3, pipeline=1),
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=2, pipeline=2),
-                                    dict(use_graph=0, wg_per_cu=1, xcd_remap=0, pipeline=2)],
+                                    dict(use_graph=0, wg_per_cu=1, xcd_remap=0, pipeline=2),
+                                    dict(use_graph=4, wg_per_cu=0, xcd_remap=32, threads=128),
+                                    dict(use_graph=5, wg_per_cu=0, xcd_remap=32, pipeline=2)],
                          ids=["eager", "persistent-xcd", "oneperbrick", "regcap", "pipelined", "pipelined-eager",
-                              "xcd-runs", "pipelined-xcd-runs", "plain-split", "plain-split-persistent"])
+                              "xcd-runs", "pipelined-xcd-runs", "plain-split", "plain-split-persistent",
+                              "graph-4-steps", "graph-5-steps-split"])
 def test_launch_configurations_bitwise_equal(elbm, launch):
     sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
     g0, o = pair(elbm, sp, "f32", 6)
