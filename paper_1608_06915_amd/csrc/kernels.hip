@@ -310,9 +310,10 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherA
 // column) pair is one lane's task, accumulating that column over the node's stencil
 // (the lanes of a node share its entry count, so a wavefront runs no idle
 // iterations); the sums go back to LDS over the rows and one lane per node collides.
-// Ring nodes are handled by the trailing workgroups.
+// Ring nodes are handled by the leading workgroups.
 constexpr int COUPLE_LDS_BYTES = 48 * 1024;
 constexpr int COUPLE_THREADS = 256;
+static_assert(BN <= COUPLE_THREADS, "the collision phase of a tile takes one node per thread");
 template <int D, typename T> __host__ __device__ constexpr int couple_rows() {
   return COUPLE_LDS_BYTES / (lds_stride<D, T>() * (int)sizeof(T));
 }
@@ -332,6 +333,28 @@ template <int D, int ST> __device__ inline void couple_finish(const CoupleArgs &
   if (L.gamma && (a.flags & FL_GAMMA)) L.gamma[(size_t)c.brick * BN + c.node] = (float)g;
 }
 
+// the same for a node of a tile: the level is uniform over the workgroup, so its
+// constants are scalar loads
+template <int D, int ST> __device__ inline void couple_finish_u(const CoupleArgs &a, cptr<LevelStatic> Lc, int lvl,
+                                                               const CItem &c, typename Codec<ST>::T (&h)[nq<D>()]) {
+  using C = Codec<ST>;
+  using S = typename C::S;
+  using T = typename C::T;
+  constexpr int Q = nq<D>();
+  T F[3] = {T(Lc->F[0]), T(Lc->F[1]), T(Lc->F[2])};
+  const float *force = Lc->force;
+  if (force) {
+    const float *fp = force + (size_t)c.brick * D * BN + c.node;
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[k] += T(fp[k * BN]) * T(Lc->fscale);
+  }
+  const bool hf = (F[0] != T(0)) || (F[1] != T(0)) || (F[2] != T(0));
+  S *o = (S *)a.dst[lvl] + (size_t)c.brick * Q * BN + c.node;
+  const T g = kbc_collide<D, T>(h, T(Lc->beta), F, hf, [&](int i, T v) { C::st(o + i * BN, v, T(wgt<D>(i))); });
+  float *gam = Lc->gamma;
+  if (gam && (a.flags & FL_GAMMA)) gam[(size_t)c.brick * BN + c.node] = (float)g;
+}
+
 template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F64 ? 2 : 4) void k_couple(CoupleArgs a) {
   using C = Codec<ST>;
   using T = typename C::T;
@@ -344,34 +367,68 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
   constexpr int TPT = (BN * NV + NT - 1) / NT;  // column tasks per lane (a tile holds at most BN nodes)
   extern __shared__ __align__(16) unsigned char couple_lds[];
   T *rows = (T *)couple_lds;
-  if ((int)blockIdx.x < a.n_tiles) {
-    const CTile t = a.tiles[blockIdx.x];
+  // ring workgroups first: each is one long dependent chain (27 pulls, then the
+  // collision) and would otherwise form the tail of the launch
+  const int ring_blocks = (a.n_ring + NT - 1) / NT;
+  const int tb = (int)blockIdx.x - ring_blocks;
+  if (tb >= 0) {
+    const CTile t = a.tiles[tb];
     const V *stage = (const V *)a.stage;
     // entries packed to 4 bytes: tile-local row (16 bits) and the weight in FP16 (the
     // weights are products of -1/16, 9/16 and 1: exact in FP16); the row area also
     // holds the per-node sums of the last phase
     const int rcap = a.lds_rows > a.lds_items ? a.lds_rows : a.lds_items;
     uint32_t *ents = (uint32_t *)(rows + (size_t)rcap * SL);
-    for (int k = threadIdx.x; k < t.npt * NV; k += NT) {
-      const int r = k / NV, q = k - r * NV;
-      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * NV + q];
+    const int tid = (int)threadIdx.x;
+    const int ntask = t.nitem * NV, nrow = t.npt * NV;
+    // every global load of the tile is issued before the first barrier, none waiting on
+    // another but the staged rows on their indices: the record of the node this lane
+    // collides, the stencil ranges of its column tasks, the row indices and entries
+    CItem cn;
+    if (tid < t.nitem) cn = a.items[t.item0 + tid];
+    int ea[TPT], eb[TPT];
+#pragma unroll
+    for (int p = 0; p < TPT; ++p) {
+      const int k = p * NT + tid;
+      ea[p] = eb[p] = 0;
+      if (k < ntask) {
+        const CItem c = a.items[t.item0 + k / NV];
+        ea[p] = c.a - t.e0;
+        eb[p] = c.b;
+      }
     }
-    for (int k = threadIdx.x; k < t.ne; k += NT) {
-      const StencilEntry s = a.sten[t.e0 + k];
-      ents[k] = (uint32_t)s.slot | ((uint32_t)__half_as_ushort(__float2half_rn(s.w)) << 16);
+    constexpr int RC = 8;  // row columns and entries per lane per round
+    for (int k0 = 0; k0 < nrow || k0 < t.ne; k0 += RC * NT) {
+      int ri[RC];
+      StencilEntry se[RC];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * NT + tid;
+        ri[j] = k < nrow ? a.tile_rows[t.pt0 + k / NV] : 0;
+        if (k < t.ne) se[j] = a.sten[t.e0 + k];
+      }
+      V rv[RC];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * NT + tid;
+        if (k < nrow) rv[j] = stage[(size_t)ri[j] * NV + k % NV];
+      }
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * NT + tid;
+        if (k < nrow) ((V *)rows)[(k / NV) * (SL / 4) + k % NV] = rv[j];
+        if (k < t.ne) ents[k] = (uint32_t)se[j].slot | ((uint32_t)__half_as_ushort(__float2half_rn(se[j].w)) << 16);
+      }
     }
     __syncthreads();
-    const int ntask = t.nitem * NV;
     T ax[TPT], ay[TPT], az[TPT], aw[TPT];
 #pragma unroll
     for (int p = 0; p < TPT; ++p) {
       ax[p] = ay[p] = az[p] = aw[p] = T(0);
-      const int k = p * NT + (int)threadIdx.x;
+      const int k = p * NT + tid;
       if (k < ntask) {
-        const int node = k / NV, col = k - node * NV;
-        const CItem c = a.items[t.item0 + node];
-        const int e1 = c.a - t.e0 + c.b;
-        for (int e = c.a - t.e0; e < e1; ++e) {
+        const int col = k % NV;
+        for (int e = ea[p]; e < ea[p] + eb[p]; ++e) {
           const uint32_t s = ents[e];
           const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
           const V r = ((const V *)(rows + (s & 0xffffu) * SL))[col];
@@ -397,10 +454,10 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
       }
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < t.nitem; it += NT) {
-      const CItem c = a.items[t.item0 + it];
+    if (tid < t.nitem) {  // a tile holds at most BN = NT nodes
+      const int lvl = __builtin_amdgcn_readfirstlane((int)cn.level);
       T acc[SW];
-      const V *row = (const V *)(rows + it * SL);
+      const V *row = (const V *)(rows + tid * SL);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const V r = row[v];
@@ -414,11 +471,11 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
       eq_dev<D, T>(acc[0], u, q);
 #pragma unroll
       for (int i = 0; i < Q; ++i) h[i] = acc[1 + D + i] + T(wgt<D>(i)) * q[i];
-      couple_finish<D, ST>(a, c, h);
+      couple_finish_u<D, ST>(a, cst(a.lev) + lvl, lvl, cn, h);
     }
     return;
   }
-  const int t = ((int)blockIdx.x - a.n_tiles) * blockDim.x + threadIdx.x;
+  const int t = (int)blockIdx.x * NT + (int)threadIdx.x;
   if (t >= a.n_ring) return;
   const CItem c = a.ring[t];
   const int fl = c.level + 1;
