@@ -428,14 +428,28 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
       const int k = p * NT + tid;
       if (k < ntask) {
         const int col = k % NV;
-        for (int e = ea[p]; e < ea[p] + eb[p]; ++e) {
-          const uint32_t s = ents[e];
+        auto acc1 = [&](uint32_t s, const V &r) {
           const T w = T(__half2float(__ushort_as_half((uint16_t)(s >> 16))));
-          const V r = ((const V *)(rows + (s & 0xffffu) * SL))[col];
           ax[p] = fma(w, r.x, ax[p]);
           ay[p] = fma(w, r.y, ay[p]);
           az[p] = fma(w, r.z, az[p]);
           aw[p] = fma(w, r.w, aw[p]);
+        };
+        auto row = [&](uint32_t s) { return ((const V *)(rows + (s & 0xffffu) * SL))[col]; };
+        int e = ea[p];
+        const int e1 = ea[p] + eb[p];
+        // four entries, then their four rows, in flight at once; summed in entry order
+        for (; e + 4 <= e1; e += 4) {
+          const uint32_t s0 = ents[e], s1 = ents[e + 1], s2 = ents[e + 2], s3 = ents[e + 3];
+          const V r0 = row(s0), r1 = row(s1), r2 = row(s2), r3 = row(s3);
+          acc1(s0, r0);
+          acc1(s1, r1);
+          acc1(s2, r2);
+          acc1(s3, r3);
+        }
+        for (; e < e1; ++e) {
+          const uint32_t s0 = ents[e];
+          acc1(s0, row(s0));
         }
       }
     }
