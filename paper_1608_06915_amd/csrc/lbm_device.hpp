@@ -298,32 +298,43 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
     if (nz == 2) return (z == 0) ? T(x * y) * pxy : ((y == 0) ? T(x * z) * pxz : T(y * z) * pyz);
     return T(0);
   };
-  // entropic scalar products <ds|dh>, <dh|dh> with weight 1/f^eq = (1/(rho W)) prod 1/phi
+  // entropic scalar products <ds|dh>, <dh|dh> with weight 1/f^eq_i.  The lattice
+  // weights are products of the 1-D weights w(0) = 2/3, w(+-1) = 1/6, so
+  // 1/f^eq_i = ir * prod_a 1/(w(c_a) (1 + a_a(c_a))): one reciprocal per axis and
+  // velocity component, the density folded into the last axis, one product per
+  // population.  The sums run as three fused multiply-add chains (by c_z; by c_y in 2-D).
   T A = 0, B = 0;
   {
-    T rxy[9], rz[3] = {1, 1, 1};
+    T r0[3], r1[3], r2[3] = {1, 1, 1};
 #pragma unroll
-    for (int cx = 0; cx < 3; ++cx) {
-      const T rx = rcp(T(1) + a[0][cx]);
-#pragma unroll
-      for (int cy = 0; cy < 3; ++cy) rxy[cx + 3 * cy] = rx * rcp(T(1) + a[1][cy]);
+    for (int k = 0; k < 3; ++k) {
+      const T w = k == 1 ? T(2.0 / 3.0) : T(1.0 / 6.0);
+      r0[k] = rcp(fma(w, a[0][k], w));
+      r1[k] = rcp(fma(w, a[1][k], w));
+      if (D == 3) r2[k] = ir * rcp(fma(w, a[2][k], w));
+      else r1[k] *= ir;
     }
-    if (D == 3)
+    T rxy[9];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rz[c] = rcp(T(1) + a[2][c]);
-    auto ifq = [&](int i) -> T {
-      T v = (ir * T(1.0 / wgt<D>(i))) * rxy[(cxo(i) + 1) + 3 * (cyo(i) + 1)];
-      if (D == 3) v *= rz[czo<D>(i) + 1];
-      return v;
-    };
-    A = tsum<D, P_SHEAR, T>([&](int i) {
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) rxy[cx + 3 * cy] = r0[cx] * r1[cy];
+    T Ap[3] = {0, 0, 0}, Bp[3] = {0, 0, 0};
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
+      constexpr int lane = D == 3 ? cz + 1 : cy + 1;
+      T ifq = rxy[(cx + 1) + 3 * (cy + 1)];
+      if (D == 3) ifq *= r2[cz + 1];
       const T ds = dsv(i);
-      return ds * (h[i] - ds) * ifq(i);
+      const T dh = h[i] - ds;
+      const T t = dh * ifq;
+      Bp[lane] = fma(t, dh, Bp[lane]);
+      if constexpr (cx * cx + cy * cy + cz * cz == 1 || cx * cx + cy * cy + cz * cz == 2)
+        Ap[lane] = fma(t, ds, Ap[lane]);  // the shear part ds is nonzero
     });
-    B = tsum<D, P_ALL, T>([&](int i) {
-      const T dh = h[i] - dsv(i);
-      return dh * dh * ifq(i);
-    });
+    A = Ap[0] + Ap[1] + Ap[2];
+    B = Bp[0] + Bp[1] + Bp[2];
   }
   const T ib = rcp(beta);
   T gamma = T(2);
@@ -331,7 +342,19 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
     const T g = ib - (T(2) - ib) * (A * rcp(B));
     if (isfinite(g)) gamma = g;
   }
-  const T b2 = T(2) * beta, bg = beta * gamma;
+  // h' = W q' + d - 2 beta ds - beta gamma (d - ds) = W q' + c1 d + c2 ds, with c2 ds
+  // taking six distinct values (q' the equilibrium of the forced velocity, if any)
+  // (each written so that only one evaluation is possible: contraction of a product into
+  // a sum is up to the compiler, and every instance of this function must round alike)
+  const T c1 = fma(-beta, gamma, T(1)), c2 = beta * (gamma - T(2));
+  const T c2sX = c2 * sX, c2sY = c2 * sY, c2sZ = c2 * sZ, c2pxy = c2 * pxy, c2pxz = c2 * pxz, c2pyz = c2 * pyz;
+  auto c2ds = [&](int i) -> T {
+    const int x = cxo(i), y = cyo(i), z = czo<D>(i);
+    const int nz = x * x + y * y + z * z;
+    if (nz == 1) return x ? c2sX : (y ? c2sY : c2sZ);
+    if (nz == 2) return (z == 0) ? T(x * y) * c2pxy : ((y == 0) ? T(x * z) * c2pxz : T(y * z) * c2pyz);
+    return T(0);
+  };
   T qxy[9];
   q_table(drho, a, qxy);
   if (has_force) {
@@ -343,18 +366,10 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
     T qxy2[9];
     q_table(drho, a2, qxy2);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T ds = dsv(i), d = h[i];
-      const T q = q_of<D>(qxy, a, i);
-      const T q2 = q_of<D>(qxy2, a2, i);
-      st(i, T(wgt<D>(i)) * q2 + (d - b2 * ds - bg * (d - ds)));
-    }
+    for (int i = 0; i < Q; ++i) st(i, fma(c1, h[i], fma(T(wgt<D>(i)), q_of<D>(qxy2, a2, i), c2ds(i))));
   } else {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T ds = dsv(i), d = h[i];
-      st(i, T(wgt<D>(i)) * q_of<D>(qxy, a, i) + (d - b2 * ds - bg * (d - ds)));
-    }
+    for (int i = 0; i < Q; ++i) st(i, fma(c1, h[i], fma(T(wgt<D>(i)), q_of<D>(qxy, a, i), c2ds(i))));
   }
   return gamma;
 }
