@@ -245,6 +245,52 @@ template <int D, typename T> __device__ inline void moments(const T (&h)[nq<D>()
   j[2] = D == 3 ? tsum<D, P_ZP, T>(v) - tsum<D, P_ZN, T>(v) : T(0);
 }
 
+// Density, momentum and second moments of h by an axis cascade (sums over c_z, then
+// c_y, then c_x, keeping the orders needed): drho = sum h, j = sum c h,
+// m2 = {sum c_x^2 h, sum c_y^2 h, sum c_z^2 h, sum c_x c_y h, sum c_x c_z h, sum c_y c_z h}.
+template <int D, typename T>
+__device__ inline void hmoments(const T (&h)[nq<D>()], T &drho, T (&j)[3], T (&m2)[6]) {
+  T H[3][3][3];  // h by velocity (c_x + 1, c_y + 1, c_z + 1)
+  static_for<0, nq<D>()>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    H[cxo(i) + 1][cyo(i) + 1][czo<D>(i) + 1] = h[i];
+  });
+  // per x: sums over y of the z-moments 0, 1, 2 (0 and 1 also with weight c_y, 0 with c_y^2)
+  T t0[3], ty[3], tyy[3], z1[3], z1y[3], z2[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    T s0[3], s1[3], s2[3];  // by y: sum_z h, sum_z c_z h, sum_z c_z^2 h
+#pragma unroll
+    for (int y = 0; y < 3; ++y) {
+      if (D == 3) {
+        s2[y] = H[x][y][2] + H[x][y][0];
+        s1[y] = H[x][y][2] - H[x][y][0];
+        s0[y] = s2[y] + H[x][y][1];
+      } else {
+        s0[y] = H[x][y][1];
+        s1[y] = s2[y] = T(0);
+      }
+    }
+    tyy[x] = s0[2] + s0[0];
+    ty[x] = s0[2] - s0[0];
+    t0[x] = tyy[x] + s0[1];
+    z1[x] = (s1[2] + s1[0]) + s1[1];
+    z1y[x] = s1[2] - s1[0];
+    z2[x] = (s2[2] + s2[0]) + s2[1];
+  }
+  const T c0 = t0[2] + t0[0];
+  drho = c0 + t0[1];
+  j[0] = t0[2] - t0[0];
+  j[1] = (ty[2] + ty[0]) + ty[1];
+  j[2] = (z1[2] + z1[0]) + z1[1];
+  m2[0] = c0;
+  m2[1] = (tyy[2] + tyy[0]) + tyy[1];
+  m2[2] = (z2[2] + z2[0]) + z2[1];
+  m2[3] = ty[2] - ty[0];
+  m2[4] = z1[2] - z1[0];
+  m2[5] = (z1y[2] + z1y[0]) + z1y[1];
+}
+
 // ---------------------------------------------------------------- KBC collision
 // Post-collision h' = h - beta (2 ds + gamma dh) (Eq. f_equations with Eq. f_mirr),
 // gamma from Eq. gamma_min_approx, plus the exact-difference forcing of Sec. III.A.
@@ -253,8 +299,8 @@ template <int D, typename T> __device__ inline void moments(const T (&h)[nq<D>()
 template <int D, typename T, typename Store>
 __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_force, Store st) {
   constexpr int Q = nq<D>();
-  T drho, j[3];
-  moments<D, T>(h, drho, j);
+  T drho, j[3], m2[6];
+  hmoments<D, T>(h, drho, j, m2);
   const T ir = rcp(T(1) + drho);
   const T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
   T a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -267,18 +313,21 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
 #pragma unroll
     for (int i = 0; i < Q; ++i) h[i] -= T(wgt<D>(i)) * q_of<D>(qxy, a, i);
   }
-  // deviatoric second moments of d
-  auto v = [&](int i) { return h[i]; };
+  // deviatoric second moments of d = f - f^eq: those of h less those of the product
+  // equilibrium, which are exact: sum_i W_i q_i c_a^2 = (1 + drho)(1/3 + 2 sig_a / 3) - 1/3
+  // and sum_i W_i q_i c_a c_b = (1 + drho) u_a u_b = j_a u_b, with sig_a = -a[a][1] the
+  // axis factor's sigma (the 1/3 of the lattice weights cancels in the differences)
+  const T r23 = (T(1) + drho) * T(2.0 / 3.0);
   T N1, N2 = 0, Pxz = 0, Pyz = 0;
   if constexpr (D == 2) {
-    N1 = tsum<D, P_XYP, T>(v) - tsum<D, P_XYN, T>(v);
+    N1 = fma(-r23, a[1][1] - a[0][1], m2[0] - m2[1]);
   } else {
-    N1 = tsum<D, P_XZP, T>(v) - tsum<D, P_XZN, T>(v);
-    N2 = tsum<D, P_YZP, T>(v) - tsum<D, P_YZN, T>(v);
-    Pxz = tsum<D, P_MXZP, T>(v) - tsum<D, P_MXZN, T>(v);
-    Pyz = tsum<D, P_MYZP, T>(v) - tsum<D, P_MYZN, T>(v);
+    N1 = fma(-r23, a[2][1] - a[0][1], m2[0] - m2[2]);
+    N2 = fma(-r23, a[2][1] - a[1][1], m2[1] - m2[2]);
+    Pxz = fma(-j[0], u[2], m2[4]);
+    Pyz = fma(-j[1], u[2], m2[5]);
   }
-  const T Pxy = tsum<D, P_MXYP, T>(v) - tsum<D, P_MXYN, T>(v);
+  const T Pxy = fma(-j[0], u[1], m2[3]);
   // shear-part values (natural-moment basis, trace in h)
   T sX, sY, sZ = 0;
   if (D == 2) {
