@@ -117,6 +117,34 @@ def fine_equiv_updates(lat, sp):
     return sum(lat.level_info(l)[1] * (1 << l) for l in range(sp.levels))
 
 
+def owned_fine_equiv_updates(lat, sp):
+    """The owned-node variant: level-l nodes counted by their owned volume (coarse units,
+    child nodes 2^-D each, the overlap split at the cut), converted back to level-l
+    nodes and weighted by the level's 2^l substeps."""
+    return sum(float(np.nansum(lat.weights(l))) * (1 << (l * sp.D)) * (1 << l) for l in range(sp.levels))
+
+
+def copy_ceiling_gbs(mib=1024, reps=10):
+    """Read+write bandwidth of a plain device-to-device copy (the practical HBM ceiling)."""
+    import torch
+
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    gbs = 2 * (mib << 20) * reps / (s.elapsed_time(e) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def run_gpu(sp, storage, steps, warmup, tune, launch=None):
     import torch
 
@@ -306,6 +334,7 @@ def main():
                    "fine_equiv_updates_per_step": fe, "storage": args.storage, "compute": "f32" if
                    args.storage != "f64" else "f64", "launch": lat.get_launch()},
         "hbm_pct_alg": round(hbm_pct, 2),
+        "mlups_fe_owned": round(owned_fine_equiv_updates(lat, sp) * args.steps / (ms / 1e3) / 1e6, 2),
         "stable": ok,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
@@ -314,6 +343,9 @@ def main():
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
                      "bytes_per_node_update": 2 * sp.Q * sbytes},
     }
+    cc = copy_ceiling_gbs()
+    out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
+    print("bench: plain device copy %.0f GB/s (read + write)" % cc, file=sys.stderr, flush=True)
     if not args.no_half and args.storage == "f32":
         lat2, ms2, sc2, nl2, _, ok2 = run_gpu(sp, "f16s", args.steps, args.warmup, not args.no_tune)
         v2 = fe * args.steps / (ms2 / 1e3) / 1e6

@@ -111,8 +111,8 @@ def test_survey_workload_node_counts(elbm):
 
 def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
     """Every entry of the committed tuning cache parses in the elbm_tune format, holds a
-    configuration elbm_set_launch accepts, and its key is the full-size channel's shape
-    (dimension, storage, bricks per level) in FP32 or FP16-shifted storage."""
+    configuration elbm_set_launch accepts, and its key is the shape (dimension, storage,
+    bricks per level) of a full-size workload: the channel, the sphere or the forest."""
     import re
 
     pat = re.compile(r'^\s*"([^"]+)": \[(-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+)\]\s*$')
@@ -123,13 +123,13 @@ def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
                 m = pat.match(line)
                 assert m, "unparsable cache line: %r" % line
                 entries[m.group(1)] = [int(v) for v in m.groups()[1:]]
-    sp = synth.channel3d()
     keys = set()
-    for st in ("f32", "f16s"):
-        g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, st)
+    for sp in (synth.channel3d(), synth.sphere3d(), synth.forest3d()):
+        g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
         synth.apply(sp, g)
-        keys.add("d%ds%d" % (sp.D, elbm.STORAGE[st]) + "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels)))
-    assert set(entries) == keys
+        shape = "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels))  # bricks do not depend on storage
+        keys |= {"d%ds%d" % (sp.D, elbm.STORAGE[st]) + shape for st in ("f32", "f16s")}
+    assert set(entries) <= keys and len(entries) == 5
     for graph, wg, xcd, thr, occ, pipe in entries.values():
         assert 0 <= graph <= 64 and 0 <= wg <= 64 and 0 <= xcd <= 4096 and thr in (64, 128, 256)
         assert occ in (1, 4) and pipe in (0, 1, 2)
