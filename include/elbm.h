@@ -169,8 +169,9 @@ elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
  * G in 2..64: graphs of G coarse steps, single-step graphs for the remainder of an
  * elbm_advance), workgroups per CU
  * for the persistent stream-collide grid (0: one workgroup per brick), XCD-aware
- * brick-to-workgroup mapping (0: none; 1: one contiguous range of bricks per XCD;
- * B in 2..4096: runs of B consecutive bricks per XCD, dealt round-robin), threads per workgroup (64, 128 or 256; each thread
+ * brick-to-workgroup mapping (0: none; 1: each XCD takes the bricks of its slab of each
+ * level along the slowest brick axis, by a table built at finalize; B in 2..4096: runs of
+ * B consecutive bricks per XCD, dealt round-robin), threads per workgroup (64, 128 or 256; each thread
  * covers 256/threads nodes of its brick), register-budget variant of the
  * stream-collide kernel (1: uncapped, 4: at most 128 VGPRs for 4 waves per SIMD),
  * pipeline (plain bricks -- every node fluid with bulk links only -- in a kernel of

@@ -85,6 +85,9 @@ struct Tick {
   int lmin;
   size_t sc_off, sc_n, gp_off, gp_n, tile_off, tile_n, ring_off, ring_n;
   size_t sc_plain;  // the last sc_plain items of the tick are plain bricks
+  // XCD tables (xcd_remap 1): item of each dispatch position for the whole tick, for its
+  // special bricks and for its plain bricks (offsets into perm_all)
+  size_t pu_off, ps_off, pp_off;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -103,6 +106,7 @@ struct elbm_ctx {
   std::vector<Pair> pairs;
   std::vector<Tick> ticks;
   std::vector<WorkItem> sc_all, red_items;
+  std::vector<int32_t> perm_all;
   std::vector<GPoint> gp_all;
   std::vector<CItem> fine_all, ring_all;
   std::vector<CTile> tiles_all;
@@ -113,7 +117,7 @@ struct elbm_ctx {
   bool finalized = false, bound = false;
   std::string err;
   // workspace layout
-  size_t ws_need = 0, o_levstatic = 0, o_pairstatic = 0, o_sc = 0, o_gp = 0, o_fine = 0, o_ring = 0, o_tiles = 0,
+  size_t ws_need = 0, o_levstatic = 0, o_pairstatic = 0, o_sc = 0, o_perm = 0, o_gp = 0, o_fine = 0, o_ring = 0, o_tiles = 0,
          o_trows = 0, o_sten = 0, o_stage = 0, o_redit = 0, o_part = 0, o_res = 0, o_tmp = 0;
   size_t tmp_bytes = 0;
   char *ws = nullptr;
@@ -862,6 +866,7 @@ elbm_status build_pairs(elbm_ctx *c) {
 void build_schedule(elbm_ctx *c) {
   c->ticks.clear();
   c->sc_all.clear();
+  c->perm_all.clear();
   c->gp_all.clear();
   c->fine_all.clear();
   c->ring_all.clear();
@@ -920,6 +925,37 @@ void build_schedule(elbm_ctx *c) {
     auto mid = std::stable_partition(c->sc_all.begin() + tk.sc_off, c->sc_all.end(),
                                      [](const WorkItem &w) { return (w.flags & WI_PLAIN) == 0; });
     tk.sc_plain = (size_t)(c->sc_all.end() - mid);
+    // XCD tables: workgroup q runs on XCD q mod 8, so position q takes a brick of group
+    // q mod 8, the groups being slabs of each level along its slowest brick axis (z in
+    // 3-D, y in 2-D) -- a brick's neighbours then share its XCD's L2 -- in item order
+    // within a group (costlier bricks first); a group that runs out is helped by the
+    // longest one
+    auto table = [&](size_t r0, size_t n) {
+      std::vector<std::vector<int32_t>> grp(8);
+      for (size_t i = 0; i < n; ++i) {
+        const WorkItem &w = c->sc_all[tk.sc_off + r0 + i];
+        const Level &L = c->lev[w.level];
+        const int ax = c->D == 3 ? 2 : 1;
+        const int64_t bz = L.borg[(size_t)w.brick * 3 + ax] / bdim(c->D, ax);
+        grp[(size_t)std::min<int64_t>(7, bz * 8 / std::max<int64_t>(1, L.gdim[ax]))].push_back((int32_t)i);
+      }
+      std::vector<size_t> head(8, 0);
+      const size_t off = c->perm_all.size();
+      for (size_t q = 0; q < n; ++q) {
+        size_t g = q % 8;
+        if (head[g] == grp[g].size()) {
+          size_t best = 0;
+          for (size_t k = 0; k < 8; ++k)
+            if (grp[k].size() - head[k] > grp[best].size() - head[best]) best = k;
+          g = best;
+        }
+        c->perm_all.push_back(grp[g][head[g]++]);
+      }
+      return off;
+    };
+    tk.pu_off = table(0, tk.sc_n);
+    tk.ps_off = table(0, tk.sc_n - tk.sc_plain);
+    tk.pp_off = table(tk.sc_n - tk.sc_plain, tk.sc_plain);
     const int p0 = std::min(lmin, pL);
     tk.gp_off = gp_start[p0];
     tk.gp_n = gp_start[pL] - tk.gp_off;
@@ -970,6 +1006,7 @@ void build_layout(elbm_ctx *c) {
   c->o_levstatic = take(sizeof(LevelStatic) * MAXL);
   c->o_pairstatic = take(sizeof(PairStatic) * MAXL);
   c->o_sc = take(c->sc_all.size() * sizeof(ItemRec));
+  c->o_perm = take(c->perm_all.size() * sizeof(int32_t));
   c->o_gp = take(c->gp_all.size() * sizeof(GPoint));
   c->o_fine = take(c->fine_all.size() * sizeof(CItem));
   c->o_ring = take(c->ring_all.size() * sizeof(CItem));
@@ -1095,6 +1132,8 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
   s.items = (const ItemRec *)(c->ws + c->o_sc) + tk.sc_off;
   s.n_items = (int)tk.sc_n;
   s.remap = c->xcd_remap;
+  const int32_t *perm = (const int32_t *)(c->ws + c->o_perm);
+  s.perm = c->xcd_remap == 1 ? perm + tk.pu_off : nullptr;
   s.flags = flags;
   s.pad = 0;
   s.lev = lev;
@@ -1116,6 +1155,8 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
   if (split) {
     sp.items = s.items + (tk.sc_n - tk.sc_plain);
     sp.n_items = (int)tk.sc_plain;
+    sp.perm = c->xcd_remap == 1 ? perm + tk.pp_off : nullptr;
+    sr.perm = c->xcd_remap == 1 ? perm + tk.ps_off : nullptr;
     cp.pipe = c->pipe;
     if (c->pipe == 1)
       cp.grid = std::min<int>((int)tk.sc_plain, (c->wg_per_cu > 0 ? c->wg_per_cu : 2) * c->cu_count);
@@ -1744,6 +1785,9 @@ elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
     }
     HIPCK(c, hipMemcpy(c->ws + c->o_sc, rec.data(), rec.size() * sizeof(ItemRec), hipMemcpyHostToDevice));
   }
+  if (!c->perm_all.empty())
+    HIPCK(c, hipMemcpy(c->ws + c->o_perm, c->perm_all.data(), c->perm_all.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
   if (!c->gp_all.empty())
     HIPCK(c, hipMemcpy(c->ws + c->o_gp, c->gp_all.data(), c->gp_all.size() * sizeof(GPoint), hipMemcpyHostToDevice));
   if (!c->fine_all.empty())

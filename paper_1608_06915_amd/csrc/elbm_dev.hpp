@@ -107,12 +107,13 @@ enum { FL_DRAG = 1, FL_GAMMA = 2 };
 struct SCArgs {
   const ItemRec *items;
   int32_t n_items;
-  int32_t remap;  // XCD-aware item mapping (0 identity, 1 contiguous ranges, B >= 2 runs of B items)
+  int32_t remap;  // XCD-aware item mapping (0 identity, 1 by perm, B >= 2 runs of B items)
   int32_t flags;  // FL_DRAG: accumulate momentum exchange, FL_GAMMA: write gamma
   int32_t pad;
   const LevelStatic *lev;
   void *src[MAXL];
   void *dst[MAXL];
+  const int32_t *perm;  // item of dispatch position q (remap 1), else null
 };
 
 struct GatherArgs {

@@ -32,8 +32,9 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
   const int G = gridDim.x;
   const int me = xcd_item(blockIdx.x, G, a.remap);
   for (int base = 0; base < a.n_items; base += G) {
-    const int idx = base + me;
-    if (idx >= a.n_items) break;
+    const int q = base + me;
+    if (q >= a.n_items) break;
+    const int idx = a.perm ? cst(a.perm)[q] : q;
     // the item, its level's constants and its neighbour bricks are wave-uniform:
     // scalar loads, issued together, with no dependent vector round trip
     cptr<ItemRec> rec = cst(a.items) + idx;
@@ -246,7 +247,9 @@ template <int D, int ST> __global__ __launch_bounds__(256, 2) void k_sc_pipe(SCA
     const int m = cnt - c0 < PIPE_RECS ? cnt - c0 : PIPE_RECS;
     for (int t = threadIdx.x; t < m * 32; t += blockDim.x) {
       const int r = t >> 5, q = t & 31;
-      ((uint32_t *)srec)[t] = ((const uint32_t *)(a.items + me + (size_t)(c0 + r) * G))[q];
+      const int pos = me + (c0 + r) * G;
+      const int idx = a.perm ? a.perm[pos] : pos;
+      ((uint32_t *)srec)[t] = ((const uint32_t *)(a.items + idx))[q];
     }
     __syncthreads();
     S hA[Q], hB[Q];

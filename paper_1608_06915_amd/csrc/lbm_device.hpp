@@ -41,6 +41,13 @@ __device__ inline Rsrc buf_rsrc(const void *base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
 
+// Cache policy of the population stores through buffer resources.  FP64 and FP32:
+// non-temporal (the NT bit of the gfx94x cache-policy operand) -- a stored population
+// is read only by the next launch, so it streams past the L2 (measured: stream-collide
+// 63 -> 60 us on the FP32 channel).  16-bit storage: default policy (non-temporal
+// 2-byte stores measured slower).
+constexpr int ST_POLICY = 2, ST_POLICY16 = 0;
+
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
   typedef double S;
@@ -56,7 +63,7 @@ template <> struct Codec<ST_F64> {
   __device__ static inline T dec(S x, T w) { return x - w; }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
     typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) V2;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, w + h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, w + h), r, v, s, ST_POLICY);
   }
 };
 template <> struct Codec<ST_F32> {
@@ -72,7 +79,7 @@ template <> struct Codec<ST_F32> {
   }
   __device__ static inline T dec(S x, T w) { return x - w; }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T w) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, w + h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, w + h), r, v, s, ST_POLICY);
   }
 };
 template <> struct Codec<ST_F16S> {
@@ -90,7 +97,7 @@ template <> struct Codec<ST_F16S> {
     return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
-    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, ST_POLICY16);
   }
 };
 template <> struct Codec<ST_BF16S> {
@@ -113,7 +120,7 @@ template <> struct Codec<ST_BF16S> {
     return unpack(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
   __device__ static inline void stb(Rsrc r, uint32_t v, uint32_t s, T h, T) {
-    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(pack(h), r, v, s, ST_POLICY16);
   }
 };
 
@@ -694,14 +701,13 @@ template <int D> __device__ inline void node_xyz(int n, int &x, int &y, int &z) 
 }
 
 // Item of workgroup b in a grid of G.  The hardware deals workgroups round-robin to
-// the 8 XCDs (b & 7), each with its own L2.  mode 0: identity; mode 1: each XCD gets
-// one contiguous range of G/8 items (G a multiple of 8, else identity); mode B >= 2:
-// runs of B consecutive items go to one XCD and the runs are dealt round-robin, so
-// bricks that share halo lines (consecutive bricks are x-neighbours) meet in one L2
-// while every XCD still sweeps the whole item range; workgroups past the last whole
-// round of 8 runs keep their own index.  Every mode is a bijection of [0, G).
+// the 8 XCDs (b & 7), each with its own L2.  mode 0 (and 1, whose mapping is a table
+// built on the host): identity; mode B >= 2: runs of B consecutive items go to one XCD
+// and the runs are dealt round-robin, so bricks that share halo lines (consecutive
+// bricks are x-neighbours) meet in one L2 while every XCD still sweeps the whole item
+// range; workgroups past the last whole round of 8 runs keep their own index.  Every
+// mode is a bijection of [0, G).
 __device__ inline int xcd_item(int b, int G, int mode) {
-  if (mode == 1) return (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
   if (mode >= 2) {
     const int round = 8 * mode;
     if (b < G / round * round) {
