@@ -494,38 +494,6 @@ __device__ inline void pull_plain(const char *__restrict__ srcb, OFF boff, const
   }
 }
 
-template <int D, int ST, typename OFF>
-__device__ inline void pull_special(const char *__restrict__ srcb, OFF boff, const Lane<D> &ln, int n,
-                                    uint8_t cls, uint32_t mask, const LevelStatic &L,
-                                    typename Codec<ST>::T (&h)[nq<D>()]) {
-  using C = Codec<ST>;
-  using S = typename C::S;
-  using T = typename C::T;
-  using Bk = Brick<D>;
-  constexpr int Q = nq<D>();
-  const uint32_t own = boff(13);
-  static_for<0, Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    const bool hit = (mask >> i) & 1u;
-    if (hit && (cls & CLS_LINKS)) {  // halfway bounce-back: own node, opposite velocity
-      h[i] = C::ld((const S *)(srcb + own + (uint32_t)(((Q - 1 - i) * BN + n) * (int)sizeof(S))),
-                   T(wgt<D>(Q - 1 - i)));
-    } else if (hit && (cls & CLS_INLET)) {
-      h[i] = T(L.hin[i]);
-    } else if (hit && (cls & CLS_OUTFLOW)) {  // zero gradient: value one node upstream
-      int x = n & (Bk::BX - 1), y = (n >> Bk::LX) & (Bk::BY - 1), z = D == 3 ? n >> (Bk::LX + Bk::LY) : 0;
-      const int sx = x - cxo(i) - L.oshift[0], sy = y - cyo(i) - L.oshift[1], sz = z - czo<D>(i) - L.oshift[2];
-      const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
-      const int loc =
-          (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
-      h[i] = C::ld((const S *)(srcb + boff(code) + (uint32_t)((i * BN + loc) * (int)sizeof(S))), T(wgt<D>(i)));
-    } else {
-      const uint32_t off = boff(ln.code(i)) + (uint32_t)((i * BN + ln.local(i)) * (int)sizeof(S));
-      h[i] = C::ld((const S *)(srcb + off), T(wgt<D>(i)));
-    }
-  });
-}
-
 template <int D> struct BulkLane {
   bool xlo, xhi, ylo, yhi;  // per lane: on the low/high x (y) face of the brick
   uint32_t mxlo, mxhi, mylo, myhi;  // the same as all-ones / zero masks

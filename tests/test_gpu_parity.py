@@ -252,6 +252,40 @@ def test_channel_half_storage(elbm, storage, bound):
     assert err < bound
 
 
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_half_storage_launch_configurations_bitwise_equal(elbm, storage):
+    """16-bit storage has its own store policy and graph capture order: the cached kind of
+    launch (graphs of several steps, XCD slab table, two nodes per thread) and the split
+    mode give the same populations as the library default."""
+    sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g0, _ = pair(elbm, sp, storage, 7)
+    for launch in (dict(use_graph=3, wg_per_cu=0, xcd_remap=1, threads=128),
+                   dict(use_graph=2, wg_per_cu=0, xcd_remap=32, threads=256, pipeline=2)):
+        g1, _ = pair(elbm, sp, storage, 7, launch=launch)
+        for l in range(sp.levels):
+            assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
+
+
+def test_two_dimensional_xcd_slabs_bitwise_equal(elbm):
+    """The XCD slab table of a 2-D lattice (slabs along y), with a force field and drag."""
+    import torch
+
+    sp = synth.cylinder2d(64, 32, ((10, 8), (30, 24)), (20, 16), 8.0)
+    out = []
+    for launch in (None, dict(use_graph=4, wg_per_cu=0, xcd_remap=1, threads=256),
+                   dict(use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, pipeline=2)):
+        g, o = pair(elbm, sp, "f32", 0, launch=launch)
+        for l in range(sp.levels):
+            F = synth.rng(99 + l).uniform(-1e-6, 1e-6, size=(2,) + o.shape(l))
+            g.set_force_field(l, torch.from_numpy(F).cuda())
+        g.advance(9)
+        out.append(([g.get_f(l) for l in range(sp.levels)], g.drag(1)[0]))
+    for f, d in out[1:]:
+        for l in range(sp.levels):
+            assert np.array_equal(out[0][0][l], f[l], equal_nan=True)
+        assert np.array_equal(out[0][1], d)
+
+
 def test_deterministic_repeat(elbm):
     sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
                         centre=(20, 12, 12))
