@@ -72,6 +72,9 @@ def workload(name):
     if name == "sphere3d":
         return synth.sphere3d(), ("D3Q27 KBC flow past a sphere, 3 nested 2x levels, coarse 256x128x128, D=20 "
                                   "finest units, inlet u=0.05, outflow, Re=300")
+    if name == "sphere_paper3d":
+        return synth.sphere_paper3d(), ("D3Q27 KBC flow past a sphere at the paper's scale: 4 nested 2x levels, coarse "
+                                        "448x296x296, D=120 finest units, inlet u=0.05, outflow, Re=3700")
     if name == "forest3d":
         return synth.forest3d(), ("D3Q27 KBC periodic block forest, 4 levels, 512 blocks of 16^3 cells "
                                   "(204/154/106/48), 2:1 balanced, seeded |u|<=0.05")

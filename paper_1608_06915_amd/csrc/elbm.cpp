@@ -699,7 +699,17 @@ elbm_status build_pairs(elbm_ctx *c) {
     P.fac_pc = Lp.beta / (2.0 * Lc.beta);  // Eq. f_neq_rescaling_iso with r = 2
     P.fac_cp = 2.0 * Lc.beta / Lp.beta;
     std::unordered_map<uint64_t, int32_t> slot_of;
+    // slot of each coarse point already placed: a point is named by many stencils
+    // (up to 64 per fine node), and it always maps to the same node
+    std::unordered_map<uint64_t, int32_t> slot_at;
     auto point = [&](const int64_t X[3], int32_t &slot) -> elbm_status {
+      const uint64_t xkey = ((uint64_t)(X[0] & 0x1fffff) << 42) | ((uint64_t)(X[1] & 0x1fffff) << 21) |
+                            (uint64_t)(X[2] & 0x1fffff);
+      auto hit = slot_at.find(xkey);
+      if (hit != slot_at.end()) {
+        slot = hit->second;
+        return ELBM_OK;
+      }
       int64_t xc[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
       int lvl;
       NodeRef r;
@@ -720,6 +730,7 @@ elbm_status build_pairs(elbm_ctx *c) {
       auto it = slot_of.find(key);
       if (it != slot_of.end()) {
         slot = it->second;
+        slot_at[xkey] = slot;
         return ELBM_OK;
       }
       GPoint g;
@@ -730,6 +741,7 @@ elbm_status build_pairs(elbm_ctx *c) {
       g.slot = slots++;
       P.pts.push_back(g);
       slot_of[key] = g.slot;
+      slot_at[xkey] = g.slot;
       slot = g.slot;
       return ELBM_OK;
     };

@@ -185,6 +185,34 @@ def sphere3d(nx: int = 256, ny: int = 128, nz: int = 128, U: float = 0.05, Re: f
     return sp
 
 
+def sphere_paper3d(U: float = 0.05, Re: float = 3700.0, D_fine: float = 120.0) -> Spec:
+    """The sphere at the paper's own scale (Sec. IV, sphere at Re = 3700): four levels,
+    diameter D = 120 finest units, domain about 30D x 20D x 20D (448 x 296 x 296 coarse: the
+    largest that keeps one level's population buffer under the 4 GiB that 32-bit brick
+    offsets address), three nested boxes around the sphere and its near wake (coarse
+    coordinates below), about 96e6 nodes in all.  Inlet at x = 0, outflow at x = nx - 1,
+    periodic in y and z; uniform initial velocity U.  The box extents are this
+    workload's own (the paper does not list them)."""
+    nx, ny, nz = 448, 296, 296
+    centre = (150.0, 148.0, 148.0)
+    nu3 = U * D_fine / Re
+    nu0 = nu3 / 8.0
+    coarse_boxes = {1: ((104, 108, 108), (264, 188, 188)), 2: ((120, 122, 122), (220, 174, 174)),
+                    3: ((130, 132, 132), (190, 164, 164))}
+
+    def init(level, lo, n):
+        shp = tuple(int(v) for v in n[:3][::-1])
+        u = np.zeros((3,) + shp)
+        u[0] = U
+        return np.ones(shp), u, None
+
+    boxes = {l: [(tuple(v << l for v in b[0]), tuple(v << l for v in b[1]))] for l, b in coarse_boxes.items()}
+    return Spec("sphere_paper3d", 3, (nx, ny, nz), (False, True, True), nu0, 4, boxes,
+                faces={0: (FACE_INLET, (U, 0.0, 0.0)), 1: (FACE_OUTFLOW, (0.0, 0.0, 0.0))},
+                bodies={3: (tuple(8.0 * c for c in centre), D_fine / 2.0)}, init=init, U=U, body_level=3,
+                body_diameter=D_fine)
+
+
 def _forest(root: Tuple[int, int, int], counts: Tuple[int, ...], r: np.random.Generator):
     """Nested compact clusters of refined blocks.  Level l blocks have 16 level-l cells
     per axis; refining a block produces its 8 children.  A block is refined only if all
