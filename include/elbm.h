@@ -165,6 +165,24 @@ elbm_status elbm_drag(elbm_ctx *ctx, int level, double F[3], int64_t *steps, int
 /* Write gamma (Eq. gamma_min_approx) of every collision to a per-node buffer. */
 elbm_status elbm_set_gamma_output(elbm_ctx *ctx, int enable);
 
+/* Nodes per brick along x, y, z for dimension D (2 or 3; z is 1 in 2-D): the tiling of
+ * each level box that elbm_gamma_indicator reports on, from the level box origin.
+ * ELBM_EINVAL for another D or a NULL dims. */
+elbm_status elbm_brick_dims(int D, int64_t dims[3]);
+
+/* Under-resolution indicator from the entropic stabiliser.  Resolved flow drives gamma
+ * to its LBGK value 2, so its deviation measures under-resolution (Sec. IV, turbulent
+ * channel flow); the conclusion (Sec. V) names it as the refinement criterion of an
+ * adaptive scheme.  Writes, per brick of `level` (elbm_brick_dims), the largest
+ * |gamma - 2| over the brick's fluid nodes, gamma being that of each node's last
+ * collision, into out_dev: device float array [grid[2]][grid[1]][grid[0]] (x fastest),
+ * -1 where a brick holds no fluid node or no brick exists.  grid (host, always written)
+ * receives the brick-grid extent; out_dev may be NULL to query only that (needs a
+ * finalized context).  Caller owns out_dev.  ELBM_ESTATE before bind or when gamma
+ * output is off (elbm_set_gamma_output); ELBM_EINVAL for a bad level.  Asynchronous on
+ * the bound stream. */
+elbm_status elbm_gamma_indicator(elbm_ctx *ctx, int level, float *out_dev, int64_t grid[3]);
+
 /* Launch configuration: use_graph (0: eager launches; 1: one graph per coarse step;
  * G in 2..64: graphs of G coarse steps, single-step graphs for the remainder of an
  * elbm_advance), workgroups per CU

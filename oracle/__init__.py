@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE: the independent reference for the HIP library.  Only the test
 suite, the smoke check and the benchmark's CPU-baseline leg may import this package.
-The arithmetic lives in ``elbm_oracle.c``; this module only marshals arguments.
+The arithmetic lives in ``elbm_oracle.c``; this module marshals arguments, apart from
+``gamma_indicator``, a plain numpy reduction of the gamma field the C oracle returns.
 """
 from __future__ import annotations
 
@@ -149,6 +150,27 @@ def init_adjoint_u(D, rho, u, noise, lam):
     nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
     out = np.empty_like(u)
     lib().ora_init_adjoint_u(D, rho.size, _dp(rho), _dp(u), None if nz is None else _dp(nz), _dp(lam), _dp(out))
+    return out
+
+
+def gamma_indicator(gamma: np.ndarray, bdims) -> np.ndarray:
+    """Under-resolution indicator per block of a level: resolved flow drives the
+    stabiliser gamma of Eq. gamma_min_approx to its LBGK value 2, so |gamma - 2|
+    measures under-resolution (Sec. IV, turbulent channel flow) and serves as the
+    refinement criterion the conclusion (Sec. V) proposes.  `gamma` is a level's field
+    (z/y, ..., x order, NaN at nodes without a value), `bdims` the block extent along
+    x, y, z.  Blocks tile the field from its origin; the result holds, per block, the
+    largest |gamma - 2| over its nodes with a value, -1 for a block without any."""
+    D = gamma.ndim
+    ext = [int(bdims[a]) for a in range(D)][::-1]  # block extent in array-axis order
+    grid = [-(-gamma.shape[k] // ext[k]) for k in range(D)]
+    out = np.full(grid, -1.0)
+    for idx in np.ndindex(*grid):
+        sl = tuple(slice(idx[k] * ext[k], (idx[k] + 1) * ext[k]) for k in range(D))
+        block = gamma[sl]
+        vals = np.abs(block[np.isfinite(block)] - 2.0)
+        if vals.size:
+            out[idx] = vals.max()
     return out
 
 

@@ -34,6 +34,7 @@
 
 #include "../../include/elbm.h"
 #include "elbm_dev.hpp"
+#include "indicator.hpp"
 
 using namespace elbm;
 
@@ -1974,6 +1975,31 @@ elbm_status elbm_read_moments(elbm_ctx *c, int level, double *rho, double *u, do
   const int cur = level == 0 ? c->parity : 0;
   LCK(c, launch_read(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
                      L.nb, (const int32_t *)(c->ws + L.o_borg), box, rho, u, gamma, nullptr, c->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_brick_dims(int D, int64_t dims[3]) {
+  if ((D != 2 && D != 3) || !dims) return ELBM_EINVAL;
+  for (int a = 0; a < 3; ++a) dims[a] = bdim(D, a);
+  return ELBM_OK;
+}
+
+elbm_status elbm_gamma_indicator(elbm_ctx *c, int level, float *out, int64_t grid[3]) {
+  if (!c || !grid) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  const Level &L = c->lev[level];
+  for (int a = 0; a < 3; ++a) grid[a] = L.gdim[a];
+  if (!out) return ELBM_OK;
+  if (!c->bound) FAIL(c, ELBM_ESTATE, "indicator before bind");
+  if (!c->gamma_on) FAIL(c, ELBM_ESTATE, "the indicator reads the per-node gamma: enable elbm_set_gamma_output first");
+  Dims box, g;
+  for (int a = 0; a < 3; ++a) {
+    box.n[a] = L.bn[a];
+    g.n[a] = L.gdim[a];
+  }
+  LCK(c, launch_gamma_indicator(c->D, (const LevelStatic *)(c->ws + c->o_levstatic), level, L.nb,
+                                (const int32_t *)(c->ws + L.o_borg), box, g, out, c->stream));
   return ELBM_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "elbm_set_solid", "elbm_set_force_uniform", "elbm_finalize", "elbm_level_box", "elbm_level_info",
     "elbm_node_class", "elbm_weights", "elbm_bind", "elbm_init_fields", "elbm_set_force_field", "elbm_advance",
     "elbm_read_moments", "elbm_read_populations", "elbm_sample_populations", "elbm_reduce", "elbm_check",
-    "elbm_drag", "elbm_set_gamma_output", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
+    "elbm_drag", "elbm_set_gamma_output", "elbm_brick_dims", "elbm_gamma_indicator", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
     "elbm_state_bytes", "elbm_save_state", "elbm_load_state", "elbm_get_launch",
     "elbm_adjoint_bytes", "elbm_adjoint_bind", "elbm_adjoint_forward", "elbm_adjoint_backward",
     "elbm_adjoint_read", "elbm_adjoint_velocity", "elbm_adjoint_timing",
@@ -87,6 +87,8 @@ def lib():
             "elbm_check": [P],
             "elbm_drag": [P, i32, dp, i64p, i32],
             "elbm_set_gamma_output": [P, i32],
+            "elbm_brick_dims": [i32, i64p],
+            "elbm_gamma_indicator": [P, i32, P, i64p],
             "elbm_set_launch": [P, i32, i32, i32, i32, i32, i32],
             "elbm_tune": [P, ctypes.c_char_p, i32],
             "elbm_get_launch": [P, P],
@@ -304,6 +306,23 @@ class Lattice:
 
     def set_gamma_output(self, enable=True):
         self._ck(lib().elbm_set_gamma_output(self._h, int(enable)))
+
+    def brick_dims(self):
+        d = np.zeros(3, np.int64)
+        st = lib().elbm_brick_dims(self.D, _p64(d))
+        if st:
+            raise ElbmError(st, "elbm_brick_dims")
+        return d
+
+    def gamma_indicator(self, level):
+        """Per brick of the level, the largest |gamma - 2| over its fluid nodes (-1 where
+        a brick has none), as an array over the brick grid, z/y, ..., x order."""
+        grid = np.zeros(3, np.int64)
+        self._ck(lib().elbm_gamma_indicator(self._h, level, None, _p64(grid)))
+        out = torch.empty(int(grid.prod()), dtype=torch.float32, device=self.workspace.device)
+        self._ck(lib().elbm_gamma_indicator(self._h, level, ctypes.c_void_p(out.data_ptr()), _p64(grid)))
+        self.synchronize()
+        return out.cpu().numpy().reshape(tuple(int(v) for v in grid[: self.D][::-1]))
 
     def set_launch(self, use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, occupancy=1, pipeline=0):
         self._ck(lib().elbm_set_launch(self._h, int(use_graph), int(wg_per_cu), int(xcd_remap), int(threads),

@@ -139,6 +139,36 @@ def test_mass_momentum_and_gamma_fp64(elbm):
         assert np.max(np.abs(gg[m] - go[m]) / np.abs(go[m])) < 3e-7
 
 
+@pytest.mark.parametrize("case", ["tgv2d", "channel3d"])
+def test_gamma_indicator_matches_oracle(elbm, case):
+    """Per brick, the largest |gamma - 2| over its fluid nodes (the under-resolution
+    measure of Sec. IV / the refinement criterion of Sec. V), on the GPU against the
+    oracle's reduction of its own gamma field, FP64, every level.  Blocks without a
+    fluid node read -1 on both sides; values agree to the FP32 rounding of the stored
+    gamma."""
+    if case == "tgv2d":
+        sp = synth.tgv2d(32, (8, 24), 0.04, 0.02, noise=1e-3)
+    else:
+        sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
+    g, o = pair(elbm, sp, "f64", 12, gamma=True)
+    bd = g.brick_dims()
+    for l in range(sp.levels):
+        ig = g.gamma_indicator(l)
+        io = oracle.gamma_indicator(o.moments(l)[2], bd)
+        assert ig.shape == io.shape
+        empty = io == -1.0
+        assert np.array_equal(ig == -1.0, empty)
+        assert np.max(io[~empty]) > 1e-6  # the flow is not trivially resolved everywhere
+        assert np.max(np.abs(ig[~empty] - io[~empty])) < 5e-7
+
+
+def test_gamma_indicator_needs_gamma_output(elbm):
+    sp = synth.tgv2d(32, (8, 24), 0.04, 0.02)
+    g, _ = pair(elbm, sp, "f32", 1)
+    with pytest.raises(elbm.ElbmError):
+        g.gamma_indicator(0)
+
+
 def test_cached_launch_hit_and_miss(elbm, tmp_path):
     """A cache hit applies the stored configuration without touching the state; a miss
     returns False and leaves the configuration unchanged (no search runs)."""
