@@ -206,6 +206,10 @@ def run_adjoint(name, storage, n, K):
     lat = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
     synth.apply(sp, lat)
     lat.bind()
+    # the forward and the adjoint's checkpointed forward both take the cached launch
+    # configuration of the workload
+    if not lat.use_cached_launch(os.environ.get("ELBM_TUNE_CACHE")):
+        print("bench: adjoint workload: no cached launch configuration, library default", file=sys.stderr, flush=True)
     _init(lat, sp)
     obj, bl = ("drag", sp.body_level) if sp.body_level is not None else ("ke", 0)
     lat.adjoint_bind(n, K)
@@ -236,7 +240,7 @@ def run_adjoint(name, storage, n, K):
             "adjoint_breakdown_ms": {"forward_with_checkpoints": round(ms[0], 3), "recompute": round(ms[1], 3),
                                      "reverse": round(ms[2], 3)},
             "ratio": round(adj_ms / fwd_ms, 3), "ratio_wall": round(wall_ms / fwd_ms, 3),
-            "forward_MLUPS_fe": round(fe * n / (fwd_ms / 1e3) / 1e6, 1), "J": J}
+            "forward_MLUPS_fe": round(fe * n / (fwd_ms / 1e3) / 1e6, 1), "J": J, "launch": lat.get_launch()}
 
 
 def cpu_baseline(sp, fe_updates, steps):

@@ -112,7 +112,8 @@ def test_survey_workload_node_counts(elbm):
 def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
     """Every entry of the committed tuning cache parses in the elbm_tune format, holds a
     configuration elbm_set_launch accepts, and its key is the shape (dimension, storage,
-    bricks per level) of a full-size workload: the channel, the sphere or the forest."""
+    bricks per level) of a full-size workload: the channel, the sphere, the forest or the
+    adjoint's cylinder."""
     import re
 
     pat = re.compile(r'^\s*"([^"]+)": \[(-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+), (-?\d+)\]\s*$')
@@ -124,11 +125,12 @@ def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
                 assert m, "unparsable cache line: %r" % line
                 entries[m.group(1)] = [int(v) for v in m.groups()[1:]]
     keys = set()
-    for sp in (synth.channel3d(), synth.sphere3d(), synth.forest3d()):
+    for sp, storages in ((synth.channel3d(), ("f32", "f16s")), (synth.sphere3d(), ("f32", "f16s")),
+                         (synth.forest3d(), ("f32", "f16s")), (synth.cylinder2d(), ("f32",))):
         g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
         synth.apply(sp, g)
         shape = "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels))  # bricks do not depend on storage
-        keys |= {"d%ds%d" % (sp.D, elbm.STORAGE[st]) + shape for st in ("f32", "f16s")}
+        keys |= {"d%ds%d" % (sp.D, elbm.STORAGE[st]) + shape for st in storages}
     assert set(entries) == keys
     for graph, wg, xcd, thr, occ, pipe in entries.values():
         assert 0 <= graph <= 64 and 0 <= wg <= 64 and 0 <= xcd <= 4096 and thr in (64, 128, 256)
