@@ -295,7 +295,7 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n, "launches": 5}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; multi-GPU runs are not supported", file=sys.stderr)
         raise SystemExit(2)
 
     import torch

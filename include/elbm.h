@@ -209,7 +209,7 @@ elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[6]);
  * level 1>...".  On a hit the configuration is applied (as elbm_set_launch) and the
  * state is untouched.  On a miss the on-line search (timing `steps` coarse steps per
  * candidate, state restored, result appended to the cache) would run; it is switched
- * off in this build and a miss returns ELBM_ESTATE with the key in the error text,
+ * off in this version of the library and a miss returns ELBM_ESTATE with the key in the error text,
  * leaving the configuration unchanged. */
 elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
 /* Time `steps` coarse steps with HIP events around every stream-collide launch;

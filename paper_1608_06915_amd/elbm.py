@@ -59,8 +59,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libelbm.so not built: run __graft_entry__.build() or "
-                              "python -m paper_1608_06915_amd.build")
+            raise ImportError("libelbm.so not built: run python -m paper_1608_06915_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         P, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
         i32, i64 = ctypes.c_int, ctypes.c_int64

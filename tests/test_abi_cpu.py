@@ -100,7 +100,7 @@ def test_host_geometry_equals_oracle(elbm, case):
         assert beta == pytest.approx(obeta, rel=1e-15)
 
 
-def test_survey_workload_node_counts(elbm):
+def test_full_size_channel_node_counts(elbm):
     """Full-size channel: 128x50x64 coarse nodes and two 256x17x128 fine slabs."""
     sp = synth.channel3d()
     g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
