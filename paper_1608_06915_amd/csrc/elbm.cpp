@@ -143,7 +143,13 @@ struct elbm_ctx {
     int nmax = 0, K = 1;
     size_t o_tape[MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL] = {}, o_lF[MAXL] = {},
            o_amask[MAXL] = {}, o_alev = 0, o_astage = 0, o_tofs = 0, o_tsten = 0, o_items = 0, o_part = 0,
-           o_res = 0, need = 0;
+           o_res = 0, o_stape = 0, need = 0;
+    // staged rows of every coupling tick of a segment, kept from the recomputation for
+    // the reverse sweep: slot of tick t (-1 without coupling), slots per coarse step,
+    // bytes per slot
+    std::vector<int> ctick;
+    int nct = 0;
+    size_t stage_bytes = 0;
     bool has_amask[MAXL] = {};
     std::vector<WorkItem> items;                  // every brick of the arriving levels, per tick
     std::vector<std::pair<size_t, size_t>> tick;  // (offset, count) into items per tick
@@ -1129,7 +1135,10 @@ int src_index(int l, int p, int k) { return ((l == 0 ? p : 0) ^ ((k - 1) & 1)); 
 
 // one tick with explicit input/output buffers per level (flags: FL_DRAG, FL_GAMMA)
 elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *const dst[MAXL], hipStream_t main,
-                            hipStream_t side, bool fork, int flags) {
+                            hipStream_t side, bool fork, int flags, void *stage = nullptr) {
+  // staged rows of the tick's interpolation points: the context's buffer unless the
+  // caller keeps them (the adjoint's recomputation)
+  void *const stg = stage ? stage : (void *)(c->ws + c->o_stage);
   const Tick &tk = c->ticks[t - 1];
   const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
   const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
@@ -1148,7 +1157,7 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     g.pts = (const GPoint *)(c->ws + c->o_gp) + tk.gp_off;
     g.n = (int)tk.gp_n;
     g.stride = stage_row_width(c->D);
-    g.stage = c->ws + c->o_stage;
+    g.stage = stg;
     g.lev = lev;
     g.pairs = pairs;
     for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
@@ -1164,7 +1173,7 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     a.n_ring = (int)tk.ring_n;
     a.stride = stage_row_width(c->D);
     a.sten = (const StencilEntry *)(c->ws + c->o_sten);
-    a.stage = c->ws + c->o_stage;
+    a.stage = stg;
     a.lev = lev;
     a.pairs = pairs;
     for (int l = 0; l < MAXL; ++l) {
@@ -1435,12 +1444,25 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
   }
   A.o_alev = take(sizeof(AdjLevel) * MAXL);
   A.o_astage = take(c->fine_all.size() * stage_row_width(c->D) * tb);
+  const int T = 1 << (c->L - 1);
+  A.ctick.assign((size_t)T, -1);
+  A.nct = 0;
+  for (int t = 1; t <= T; ++t)
+    if (c->ticks[(size_t)t - 1].tile_n + c->ticks[(size_t)t - 1].ring_n > 0) A.ctick[(size_t)t - 1] = A.nct++;
+  A.stage_bytes = align_up((size_t)stage_row_width(c->D) * std::max(c->stage_cols, 1) * tb, 256);
+  A.o_stape = take((size_t)K * A.nct * A.stage_bytes);
   A.o_tofs = take(A.tofs.size() * 4);
   A.o_tsten = take(A.tsten.size() * sizeof(StencilEntry));
   A.o_items = take(A.items.size() * sizeof(WorkItem));
   A.o_part = take(c->red_items.size() * 5 * 8);
   A.o_res = take(64);
   A.need = off;
+}
+
+// staged rows of coupling tick t of coarse step k (1-based) of the current segment
+char *adj_stage(elbm_ctx *c, int k, int t) {
+  auto &A = c->adj;
+  return A.ws + A.o_stape + ((size_t)(k - 1) * A.nct + (size_t)A.ctick[(size_t)t - 1]) * A.stage_bytes;
 }
 
 char *adj_tape(elbm_ctx *c, int l, size_t slot) {
@@ -1495,15 +1517,7 @@ elbm_status adj_tick(elbm_ctx *c, int k, int t) {
   }
   LCK(c, launch_adj_collide(c->D, c->storage, a, c->stream));
   if (tk.tile_n + tk.ring_n > 0) {
-    GatherArgs g;
-    g.pts = (const GPoint *)(c->ws + c->o_gp) + tk.gp_off;
-    g.n = (int)tk.gp_n;
-    g.stride = stage_row_width(c->D);
-    g.stage = c->ws + c->o_stage;
-    g.lev = lev;
-    g.pairs = pairs;
-    for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
-    LCK(c, launch_gather(c->D, c->storage, g, c->stream));
+    // the staged rows of this tick were kept by the recomputation
     AdjCoupleArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.c.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
@@ -1516,7 +1530,7 @@ elbm_status adj_tick(elbm_ctx *c, int k, int t) {
     ca.c.n_ring = (int)tk.ring_n;
     ca.c.stride = stage_row_width(c->D);
     ca.c.sten = (const StencilEntry *)(c->ws + c->o_sten);
-    ca.c.stage = c->ws + c->o_stage;
+    ca.c.stage = adj_stage(c, k, t);
     ca.c.lev = lev;
     ca.c.pairs = pairs;
     for (int l = 0; l < MAXL; ++l) {
@@ -2453,7 +2467,8 @@ elbm_status elbm_adjoint_backward(elbm_ctx *c) {
           src[l] = adj_tape(c, l, slot);
           dst[l] = adj_tape(c, l, slot + 1);
         }
-        st = enqueue_tick_io(c, t, src, dst, c->stream, c->side, false, 0);
+        st = enqueue_tick_io(c, t, src, dst, c->stream, c->side, false, 0,
+                             A.ctick[(size_t)t - 1] >= 0 ? adj_stage(c, k, t) : nullptr);
       }
     HIPCK(c, hipEventRecord(ev[(size_t)3 * s + 1], c->stream));
     for (int k = Ks; k >= 1 && !st; --k)
