@@ -336,6 +336,7 @@ def test_deterministic_repeat(elbm):
 @pytest.mark.parametrize("name,storage,k,bound", [
     ("channel3d", "f32", 50, 1e-5),
     ("channel3d", "f16s", 50, 1e-3),
+    ("channel3d", "bf16s", 50, 3e-2),
     ("sphere3d", "f32", 20, 1e-5),
     ("forest3d", "f32", 20, 1e-5),
     ("cylinder2d", "f32", 200, 1e-5),
