@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import faulthandler
 import json
+import math
 import os
 import sys
 import time
@@ -277,6 +278,8 @@ def main():
     ap.add_argument("--launch", default=None,
                     help='fixed launch configuration as JSON, e.g. {"threads": 128} (ignores the tuning cache)')
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--drag-steps", type=int, default=0,
+                    help="after the timed steps, report the body's mean drag coefficient over this many coarse steps")
     ap.add_argument("--adjoint-workload", default="cylinder2d")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
@@ -350,6 +353,29 @@ def main():
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
                      "bytes_per_node_update": 2 * sp.Q * sbytes},
     }
+    if args.drag_steps > 0 and sp.body_level is not None:
+        # mean drag coefficient of the body over the next drag_steps coarse steps:
+        # C_d = F_x / (rho U^2 pi R^2 / 2), F the momentum exchanged per body-level step
+        bl = sp.body_level
+        R = sp.body_diameter / 2.0
+        lat.drag(bl, reset=True)
+        done, fx, nst, windows = 0, 0.0, 0, []
+        while done < args.drag_steps:
+            n = min(1000, args.drag_steps - done)
+            lat.advance(n)
+            F, k = lat.drag(bl, reset=True)  # synchronous
+            fx, nst, done = fx + F[0], nst + k, done + n
+            windows.append(round(float(2.0 * (F[0] / k) / (sp.U ** 2 * math.pi * R * R)), 5))
+            print("bench: drag window %d / %d coarse steps, C_d of the last %d: %.4f" % (done, args.drag_steps, n,
+                                                                                      windows[-1]),
+                  file=sys.stderr, flush=True)
+        cd = 2.0 * (fx / nst) / (sp.U ** 2 * math.pi * R * R)
+        before = args.warmup + 2 * args.steps  # warm-up, timed run and the profiling pass
+        out["drag"] = {"C_d": round(float(cd), 5), "after_coarse_steps": before,
+                       "window_coarse_steps": args.drag_steps, "C_d_per_1000_coarse_steps": windows,
+                       "stable": bool(lat.check())}
+        print("bench: C_d %.4f over coarse steps %d-%d" % (cd, before, before + args.drag_steps),
+              file=sys.stderr, flush=True)
     cc = copy_ceiling_gbs()
     out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
     print("bench: plain device copy %.0f GB/s (read + write)" % cc, file=sys.stderr, flush=True)
