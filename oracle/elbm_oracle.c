@@ -118,6 +118,7 @@ struct ora {
 static int fail(ora_t *o, int code, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
+#pragma omp critical(ora_fail)
   vsnprintf(o->err, sizeof(o->err), fmt, ap);
   va_end(ap);
   return code;
@@ -849,6 +850,9 @@ static void stream_level(ora_t *o, int l) {
   olevel *L = &o->lev[l];
   int Q = o->Q;
   tape_push(o, 0, l, 0);
+  /* every node writes only its own post-stream populations: the node loop may run on
+   * several threads (built with OpenMP) with identical results */
+#pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < L->nn; ++n) {
     if (L->solid[n]) continue;
     for (int i = 0; i < Q; ++i) {
@@ -878,35 +882,65 @@ static void stream_level(ora_t *o, int l) {
 /* collision of one level (right-hand side of Eq. f_equations); skip_outer leaves the
  * outer interface layer uncollided (Sec. III.C step 1).  Every collided node must have
  * all populations present. */
+/* population i of node n leaves towards a solid node (a bounce-back link) */
+static int solid_link(const ora_t *o, int l, int64_t n, int i) {
+  const olevel *L = &o->lev[l];
+  int64_t y[3];
+  for (int a = 0; a < 3; ++a) y[a] = L->pos[3 * n + a] + o->c[i][a];
+  if (!canon(o, l, y)) return 0;
+  int64_t m = node_id(o, l, y);
+  return m >= 0 && L->solid[m];
+}
+
 static int collide_level(ora_t *o, int l, int skip_outer) {
   olevel *L = &o->lev[l];
   int Q = o->Q;
   tape_push(o, 1, l, skip_outer);
-  double step_drag[3] = {0, 0, 0};
+  /* per node: 0 collided, 1 skipped, 2 collided with a solid link, 3 missing input */
+  uint8_t *st = (uint8_t *)malloc((size_t)(L->nn ? L->nn : 1));
+  /* the collisions are independent per node (several threads when built with OpenMP);
+   * the momentum-exchange sum below stays serial, in node order */
+#pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < L->nn; ++n) {
+    st[n] = 1;
     if (L->solid[n]) continue;
     if (skip_outer && L->pd[n] == 0) {
       L->vf[n] = 0;
       continue;
     }
+    int complete = 1;
     for (int i = 0; i < Q; ++i)
-      if (!L->vg[(size_t)n * Q + i])
-        return fail(o, -10, "level %d node (%lld,%lld,%lld) collides with missing population %d", l,
-                    (long long)L->pos[3 * n], (long long)L->pos[3 * n + 1], (long long)L->pos[3 * n + 2], i);
+      if (!L->vg[(size_t)n * Q + i]) complete = 0;
+    if (!complete) {
+      st[n] = 3;
+      continue;
+    }
     double F[3];
     node_force(o, l, n, F);
     L->gam[n] = ora_kbc(o->D, L->beta, &L->g[(size_t)n * Q], F, &L->f[(size_t)n * Q], NULL, NULL);
     L->vf[n] = 1;
-    /* momentum exchange on links into solid nodes (reading R10) */
-    for (int i = 0; i < Q; ++i) {
-      int64_t y[3];
-      for (int a = 0; a < 3; ++a) y[a] = L->pos[3 * n + a] + o->c[i][a];
-      if (!canon(o, l, y)) continue;
-      int64_t m = node_id(o, l, y);
-      if (m >= 0 && L->solid[m])
-        for (int a = 0; a < 3; ++a) step_drag[a] += 2.0 * o->c[i][a] * L->f[(size_t)n * Q + i];
-    }
+    st[n] = 0;
+    for (int i = 0; i < Q; ++i)
+      if (solid_link(o, l, n, i)) st[n] = 2;
   }
+  for (int64_t n = 0; n < L->nn; ++n)
+    if (st[n] == 3) {
+      int i = 0;
+      while (i < Q && L->vg[(size_t)n * Q + i]) ++i;
+      free(st);
+      return fail(o, -10, "level %d node (%lld,%lld,%lld) collides with missing population %d", l,
+                  (long long)L->pos[3 * n], (long long)L->pos[3 * n + 1], (long long)L->pos[3 * n + 2], i);
+    }
+  /* momentum exchange on links into solid nodes (reading R10), from the post-collision
+   * populations of this step */
+  double step_drag[3] = {0, 0, 0};
+  for (int64_t n = 0; n < L->nn; ++n) {
+    if (st[n] != 2) continue;
+    for (int i = 0; i < Q; ++i)
+      if (solid_link(o, l, n, i))
+        for (int a = 0; a < 3; ++a) step_drag[a] += 2.0 * o->c[i][a] * L->f[(size_t)n * Q + i];
+  }
+  free(st);
   for (int a = 0; a < 3; ++a) L->drag[a] += step_drag[a];
   L->drag_steps++;
   return 0;
@@ -971,8 +1005,13 @@ static int couple(ora_t *o, int lp) {
   uint8_t *setp = (uint8_t *)calloc((size_t)(P->nn ? P->nn : 1), 1);
   int rc = 0;
   static const double w4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
-  for (int64_t n = 0; n < C->nn && !rc; ++n) {
+  /* error code per child node; the nodes are independent (several threads when built
+   * with OpenMP), the first error in node order is returned */
+  int *crc = (int *)calloc((size_t)(C->nn ? C->nn : 1), sizeof(int));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t n = 0; n < C->nn; ++n) {
     if (C->solid[n] || C->pd[n] > 1) continue;
+    int rc = 0;
     const int64_t *x = &C->pos[3 * n];
     int npt[3] = {1, 1, 1};
     int64_t pts[3][4];
@@ -1004,20 +1043,27 @@ static int couple(ora_t *o, int lp) {
           for (int a = 0; a < 3; ++a) uu[a] += w * u[a];
           for (int i = 0; i < Q; ++i) nn_[i] += w * fn[i];
         }
-    if (rc) break;
+    if (rc) {
+      crc[n] = rc;
+      continue;
+    }
     double feq[OMAXQ];
     ora_feq(D, rr, uu, feq);
     for (int i = 0; i < Q; ++i) newc[(size_t)n * Q + i] = feq[i] + nn_[i];
     setc[n] = 1;
   }
+  for (int64_t n = 0; n < C->nn && !rc; ++n) rc = crc[n];
+  free(crc);
   /* coarse ring nodes from co-located fine nodes (inverse of Eq. f_neq_rescaling_iso) */
-  for (int64_t n = 0; n < P->nn && !rc; ++n) {
-    if (!P->ring[n]) continue;
+  int *prc = (int *)calloc((size_t)(P->nn ? P->nn : 1), sizeof(int));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t n = 0; n < P->nn; ++n) {
+    if (rc || !P->ring[n]) continue;
     int64_t xc[3] = {2 * P->pos[3 * n], 2 * P->pos[3 * n + 1], 2 * P->pos[3 * n + 2]};
     int64_t m = node_id(o, lp + 1, xc);
     if (m < 0 || C->solid[m] || !node_complete(o, C, m)) {
-      rc = fail(o, -14, "fine twin of ring node missing at level %d", lp + 1);
-      break;
+      prc[n] = fail(o, -14, "fine twin of ring node missing at level %d", lp + 1);
+      continue;
     }
     double r, u[3], fn[OMAXQ], feq[OMAXQ];
     node_macro(o, &C->g[(size_t)m * Q], &r, u, fn);
@@ -1026,6 +1072,8 @@ static int couple(ora_t *o, int lp) {
     for (int i = 0; i < Q; ++i) newp[(size_t)n * Q + i] = feq[i] + fac * fn[i];
     setp[n] = 1;
   }
+  for (int64_t n = 0; n < P->nn && !rc; ++n) rc = prc[n];
+  free(prc);
   if (!rc) {
     for (int64_t n = 0; n < C->nn; ++n)
       if (setc[n])
@@ -1045,6 +1093,41 @@ static int couple(ora_t *o, int lp) {
   free(newp);
   free(setp);
   return rc;
+}
+
+/* Sec. III.C steps 3-4 alone, for checking them in isolation: the post-stream states
+ * of the pair (lp, lp+1) are taken from dense [Q][box] arrays (a non-finite value is a
+ * missing population), coupled, and written back in place (the states after the
+ * rescaling and reconstruction; populations still missing read NaN). */
+int ora_couple_states(ora_t *o, int lp, double *gp, double *gc) {
+  if (!o->finalized) return fail(o, -2, "couple before finalize");
+  if (lp < 0 || lp + 1 >= o->L) return fail(o, -1, "bad parent level");
+  double *arr[2] = {gp, gc};
+  for (int s = 0; s < 2; ++s) {
+    olevel *L = &o->lev[lp + s];
+    int64_t tot = L->bn[0] * L->bn[1] * L->bn[2];
+    for (int64_t k = 0; k < tot; ++k) {
+      int32_t n = L->id[k];
+      if (n < 0) continue;
+      for (int i = 0; i < o->Q; ++i) {
+        double v = arr[s][i * tot + k];
+        L->g[(size_t)n * o->Q + i] = v;
+        L->vg[(size_t)n * o->Q + i] = (uint8_t)(!L->solid[n] && isfinite(v));
+      }
+    }
+  }
+  int rc = couple(o, lp);
+  if (rc) return rc;
+  for (int s = 0; s < 2; ++s) {
+    olevel *L = &o->lev[lp + s];
+    int64_t tot = L->bn[0] * L->bn[1] * L->bn[2];
+    for (int64_t k = 0; k < tot; ++k) {
+      int32_t n = L->id[k];
+      for (int i = 0; i < o->Q; ++i)
+        arr[s][i * tot + k] = (n < 0 || !L->vg[(size_t)n * o->Q + i]) ? NAN : L->g[(size_t)n * o->Q + i];
+    }
+  }
+  return 0;
 }
 
 /* Sec. III.C, applied recursively: the five steps for the pair (l, l+1) run inside

@@ -52,6 +52,9 @@ int ora_moments(const ora_t *o, int level, double *rho, double *u, double *gamma
 int ora_sample_f(const ora_t *o, int level, int64_t n, const int64_t *coords, double *out);
 int ora_reduce(const ora_t *o, double *mass, double mom[3]);
 int ora_drag(ora_t *o, int level, double F[3], int64_t *steps, int reset);
+/* Sec. III.C steps 3-4 on given post-stream states of levels lp, lp+1 (dense [Q][box],
+ * in/out; non-finite = missing population) */
+int ora_couple_states(ora_t *o, int lp, double *gp, double *gc);
 
 /* node-level primitives */
 void ora_feq(int D, double rho, const double u[3], double *feq);
