@@ -1,19 +1,23 @@
 """Throughput of the refined KBC hot path on one MI355X.
 
-Workload (default): D3Q27 KBC two-level channel -- 128x64x64 coarse nodes, periodic
-x/z, bounce-back walls in y, refined near-wall slabs 8 coarse rows deep, constant
-body force for Re_tau ~ 180, seeded 5% velocity perturbations; FP32 populations.
-One step = one coarse step of the whole refined path (two fine substeps, interface
-gather/reconstruction/coalescence, every collision), replayed as one HIP graph.
+Workload (default): D3Q27 KBC flow past a sphere -- three nested 2x levels, coarse
+256x128x128, sphere diameter 20 finest units, uniform inlet u = 0.05, outflow,
+Re = 300 -- with FP32 populations (the headline) and weight-shifted FP16 populations
+(alongside).  One step = one coarse step of the whole refined path (four finest
+ticks: every level's stream-collide, interface gather/reconstruction/coalescence,
+every collision), replayed from HIP graphs.  The four-level block forest (512 blocks
+of 16^3 cells) is measured as a second workload in both storage forms.
 
 Metric: fine-equivalent MLUPS = sum_l N_l 2^l x coarse steps / s / 1e6 (N_l: fluid
 nodes of level l), i.e. the paper's time-step-weighted "equivalent fine level
-points" per second.  Also reported: the same for weight-shifted FP16 storage, the
-dominant kernel's roofline (stream-collide, HBM bound), the adjoint/forward time
-ratio (default: two-level D2Q9 cylinder, mean drag over 2000 coarse steps,
-checkpoints every 100) and the FP64 CPU oracle on the same workload.
+points" per second; the median of five timed windows of K coarse steps each.  Also
+reported: HBM fractions (algorithmic bytes per coarse step, and the dominant
+stream-collide kernel's roofline measured with HIP events), the adjoint/forward time
+ratio (two-level D2Q9 cylinder, mean drag over 2000 coarse steps, checkpoints every
+100) and the FP64 CPU oracle on the same workload (OpenMP build on every host core,
+and single-thread).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere3d]
 """
 from __future__ import annotations
 
@@ -149,7 +153,9 @@ def copy_ceiling_gbs(mib=1024, reps=10):
     return gbs
 
 
-def run_gpu(sp, storage, steps, warmup, tune, launch=None):
+def run_gpu(sp, storage, steps, warmup, tune, launch=None, windows=5):
+    """Set up the workload, then time `windows` windows of exactly `steps` coarse
+    steps each (HIP events on the bound stream, synchronised on both sides)."""
     import torch
 
     from paper_1608_06915_amd import elbm
@@ -166,26 +172,62 @@ def run_gpu(sp, storage, steps, warmup, tune, launch=None):
     if launch:
         lat.set_launch(**launch)
     elif tune:
-        # launch configuration from the tuning cache (the on-line search is switched
-        # off in the library); the library default when the cache has none
+        # launch configuration chosen by the tuner (paper_1608_06915_amd/tune.py) and kept
+        # in the tuning cache; the library default when the cache has none
         if not lat.use_cached_launch(os.environ.get("ELBM_TUNE_CACHE")):
             print("bench: no cached launch configuration, library default", file=sys.stderr, flush=True)
-    print("bench: %s launch %s" % (storage, lat.get_launch()), file=sys.stderr, flush=True)
+    print("bench: %s %s launch %s" % (sp.name, storage, lat.get_launch()), file=sys.stderr, flush=True)
     lat.advance(warmup)
     lat.synchronize()
     torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(lat.stream)
-    lat.advance(steps)
-    end.record(lat.stream)
-    end.synchronize()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    win = []
+    for _ in range(windows):
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(lat.stream)
+        lat.advance(steps)
+        end.record(lat.stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        win.append(start.elapsed_time(end))
     # the same number of steps again with HIP events around every stream-collide
     # launch, on the stream the kernels are launched on
     tot_ms, sc_ms, n_launch = lat.profile(steps)
     ok = lat.check()
-    return lat, ms, sc_ms, n_launch, tot_ms, ok
+    return lat, win, sc_ms, n_launch, tot_ms, ok
+
+
+def measure(name, sp, storage, steps, warmup, tune, launch=None, windows=5):
+    """One workload in one storage form: throughput, HBM fractions, roofline."""
+    lat, win, sc_ms, n_launch, _, ok = run_gpu(sp, storage, steps, warmup, tune, launch, windows)
+    ms = float(np.median(win))
+    fe = fine_equiv_updates(lat, sp)
+    value = fe * steps / (ms / 1e3) / 1e6
+    counts = mode_counts(lat, sp)
+    sbytes = STORE_BYTES[storage]
+    bytes_step, launches_step, _ = sc_bytes_per_coarse_step(sp, counts, sbytes)
+    per_launch_bytes = bytes_step / launches_step
+    avg_launch_ms = sc_ms / max(n_launch, 1)
+    achieved = per_launch_bytes / (avg_launch_ms / 1e3) / 1e9
+    # whole-step HBM fraction with algorithmic bytes (every fluid node of every level
+    # reads and writes Q populations per level step)
+    step_bytes = fe * 2 * sp.Q * sbytes
+    hbm_pct = step_bytes / (ms / steps / 1e3) / 1e9 / PEAK_HBM_GBS * 100
+    print("bench: %s %s %.1f MLUPS_fe (median of %d windows), %.4f ms/step, stream-collide %.4f ms/launch %.0f GB/s, "
+          "stable=%s" % (name, storage, value, len(win), ms / steps, avg_launch_ms, achieved, ok),
+          file=sys.stderr, flush=True)
+    out = {"value": round(value, 2), "ms_per_step": round(ms / steps, 5),
+           "windows_ms": [round(w, 4) for w in win], "hbm_pct_alg": round(hbm_pct, 2),
+           "mlups_fe_owned": round(owned_fine_equiv_updates(lat, sp) * steps / (ms / 1e3) / 1e6, 2),
+           "stable": ok, "launch": lat.get_launch(),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, storage),
+                        "kernel": "k_stream_collide", "bytes_per_launch": int(per_launch_bytes),
+                        "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
+                        "bytes_per_node_update": 2 * sp.Q * sbytes}}
+    info = {"levels": sp.levels, "fluid_nodes_per_level": [lat.level_info(l)[1] for l in range(sp.levels)],
+            "fine_equiv_updates_per_step": fe}
+    return lat, out, info
 
 
 def _init(lat, sp):
@@ -244,11 +286,12 @@ def run_adjoint(name, storage, n, K):
             "forward_MLUPS_fe": round(fe * n / (fwd_ms / 1e3) / 1e6, 1), "J": J, "launch": lat.get_launch()}
 
 
-def cpu_baseline(sp, fe_updates, steps):
+def cpu_baseline(sp, fe_updates, steps, library):
+    """The FP64 oracle on the same workload: `steps` coarse steps after its set-up."""
     import oracle
 
     t0 = time.time()
-    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, library=library)
     from paper_1608_06915_amd import synth
 
     synth.apply(sp, o)
@@ -263,15 +306,37 @@ def cpu_baseline(sp, fe_updates, steps):
     return fe_updates * steps / dt / 1e6, dt, setup
 
 
+def host_cores():
+    """(threads the OpenMP oracle uses, logical CPUs this process may run on, lscpu model line)"""
+    import subprocess
+
+    import oracle
+
+    threads = oracle.omp_threads()
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return threads, avail, model
+
+
 def main():
     faulthandler.enable()  # a fatal signal prints the Python stack of every thread
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200, help="coarse steps per timed window")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--windows", type=int, default=5, help="timed windows (the median is reported)")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--workload", default="channel3d")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--workload", default="sphere3d")
+    ap.add_argument("--extra-workload", default="forest3d",
+                    help="second workload measured in FP32 and FP16s ('' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="coarse steps of the OpenMP oracle leg")
+    ap.add_argument("--cpu-steps-serial", type=int, default=1, help="coarse steps of the single-thread oracle leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-half", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the library default launch configuration (ignore the tuning cache)")
@@ -307,51 +372,33 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     sp, desc = workload(args.workload)
-    print("bench: workload=%s storage=%s steps=%d warmup=%d" % (args.workload, args.storage, args.steps,
-                                                                args.warmup), file=sys.stderr, flush=True)
+    print("bench: workload=%s storage=%s steps=%d x %d windows warmup=%d" % (
+        args.workload, args.storage, args.steps, args.windows, args.warmup), file=sys.stderr, flush=True)
     launch = json.loads(args.launch) if args.launch else None
-    lat, ms, sc_ms, n_launch, prof_ms, ok = run_gpu(sp, args.storage, args.steps, args.warmup, not args.no_tune,
-                                                    launch)
-    fe = fine_equiv_updates(lat, sp)
-    value = fe * args.steps / (ms / 1e3) / 1e6
-    counts = mode_counts(lat, sp)
-    sbytes = STORE_BYTES[args.storage]
-    bytes_step, launches_step, nodes_step = sc_bytes_per_coarse_step(sp, counts, sbytes)
-    per_launch_bytes = bytes_step / launches_step
-    avg_launch_ms = sc_ms / max(n_launch, 1)
-    achieved = per_launch_bytes / (avg_launch_ms / 1e3) / 1e9
-    # whole-step HBM fraction with algorithmic bytes (every fluid node of every level
-    # reads and writes Q populations per level step)
-    step_bytes = fe * 2 * sp.Q * sbytes
-    hbm_pct = step_bytes / (ms / args.steps / 1e3) / 1e9 / PEAK_HBM_GBS * 100
-    print("bench: %s %.1f MLUPS_fe, %.3f ms/step, stream-collide %.3f ms/launch %.0f GB/s, stable=%s" % (
-        args.storage, value, ms / args.steps, avg_launch_ms, achieved, ok), file=sys.stderr, flush=True)
+    lat, head, info = measure(args.workload, sp, args.storage, args.steps, args.warmup, not args.no_tune, launch,
+                              args.windows)
+    fe = info["fine_equiv_updates_per_step"]
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": head["value"],
         "unit": "MLUPS (fine-equivalent)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": desc, "levels": sp.levels,
-                   "fluid_nodes_per_level": [lat.level_info(l)[1] for l in range(sp.levels)],
-                   "fine_equiv_updates_per_step": fe, "storage": args.storage, "compute": "f32" if
-                   args.storage != "f64" else "f64", "launch": lat.get_launch()},
-        "hbm_pct_alg": round(hbm_pct, 2),
-        "mlups_fe_owned": round(owned_fine_equiv_updates(lat, sp) * args.steps / (ms / 1e3) / 1e6, 2),
-        "stable": ok,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(args.workload, args.storage),
-                     "kernel": "k_stream_collide", "bytes_per_launch": int(per_launch_bytes),
-                     "avg_launch_ms": round(avg_launch_ms, 5), "launches": n_launch,
-                     "bytes_per_node_update": 2 * sp.Q * sbytes},
+        "config": dict({"workload": desc}, **info, storage=args.storage,
+                       compute="f32" if args.storage != "f64" else "f64", launch=head["launch"]),
+        "windows": args.windows,
+        "windows_ms": head["windows_ms"],
+        "hbm_pct_alg": head["hbm_pct_alg"],
+        "mlups_fe_owned": head["mlups_fe_owned"],
+        "stable": head["stable"],
+        "roofline": head["roofline"],
     }
     if args.drag_steps > 0 and sp.body_level is not None:
         # mean drag coefficient of the body over the next drag_steps coarse steps:
@@ -359,44 +406,61 @@ def main():
         bl = sp.body_level
         R = sp.body_diameter / 2.0
         lat.drag(bl, reset=True)
-        done, fx, nst, windows = 0, 0.0, 0, []
+        done, fx, nst, wins = 0, 0.0, 0, []
         while done < args.drag_steps:
             n = min(1000, args.drag_steps - done)
             lat.advance(n)
             F, k = lat.drag(bl, reset=True)  # synchronous
             fx, nst, done = fx + F[0], nst + k, done + n
-            windows.append(round(float(2.0 * (F[0] / k) / (sp.U ** 2 * math.pi * R * R)), 5))
+            wins.append(round(float(2.0 * (F[0] / k) / (sp.U ** 2 * math.pi * R * R)), 5))
             print("bench: drag window %d / %d coarse steps, C_d of the last %d: %.4f" % (done, args.drag_steps, n,
-                                                                                      windows[-1]),
+                                                                                      wins[-1]),
                   file=sys.stderr, flush=True)
         cd = 2.0 * (fx / nst) / (sp.U ** 2 * math.pi * R * R)
-        before = args.warmup + 2 * args.steps  # warm-up, timed run and the profiling pass
+        before = args.warmup + (args.windows + 1) * args.steps  # warm-up, timed windows and the profiling pass
         out["drag"] = {"C_d": round(float(cd), 5), "after_coarse_steps": before,
-                       "window_coarse_steps": args.drag_steps, "C_d_per_1000_coarse_steps": windows,
+                       "window_coarse_steps": args.drag_steps, "C_d_per_1000_coarse_steps": wins,
                        "stable": bool(lat.check())}
         print("bench: C_d %.4f over coarse steps %d-%d" % (cd, before, before + args.drag_steps),
               file=sys.stderr, flush=True)
+    del lat
+    torch.cuda.empty_cache()
     cc = copy_ceiling_gbs()
     out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
     print("bench: plain device copy %.0f GB/s (read + write)" % cc, file=sys.stderr, flush=True)
-    if not args.no_half and args.storage == "f32":
-        lat2, ms2, sc2, nl2, _, ok2 = run_gpu(sp, "f16s", args.steps, args.warmup, not args.no_tune)
-        v2 = fe * args.steps / (ms2 / 1e3) / 1e6
-        b2, l2, _ = sc_bytes_per_coarse_step(sp, counts, 2)
-        a2 = (b2 / l2) / (sc2 / max(nl2, 1) / 1e3) / 1e9
-        out["f16s"] = {"value": round(v2, 2), "ms_per_step": round(ms2 / args.steps, 5),
-                       "hbm_pct_alg": round(fe * 2 * sp.Q * 2 / (ms2 / args.steps / 1e3) / 1e9 / PEAK_HBM_GBS * 100, 2),
-                       "stream_collide_GBs": round(a2, 1), "stable": ok2}
-        print("bench: f16s %.1f MLUPS_fe" % v2, file=sys.stderr, flush=True)
+    if not args.no_half and args.storage == "f32" and not launch:
+        lat2, half, _ = measure(args.workload, sp, "f16s", args.steps, args.warmup, not args.no_tune, None,
+                                args.windows)
+        out["f16s"] = half
         del lat2
+        torch.cuda.empty_cache()
+    if args.extra_workload and not launch:
+        sp2, desc2 = workload(args.extra_workload)
+        extra = {"workload": desc2}
+        for st in ("f32", "f16s") if not args.no_half else ("f32",):
+            lat3, res, info2 = measure(args.extra_workload, sp2, st, args.steps, args.warmup, not args.no_tune, None,
+                                       args.windows)
+            extra.update(info2)
+            extra[st] = res
+            del lat3
+            torch.cuda.empty_cache()
+        out[args.extra_workload] = extra
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(args.adjoint_workload, args.storage, args.adjoint_steps, args.adjoint_K)
     if not args.no_cpu:
-        mlups, dt, setup = cpu_baseline(sp, fe, args.cpu_steps)
-        out["cpu_baseline"] = {"value": round(mlups, 4), "unit": "MLUPS (fine-equivalent)", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "%d coarse steps of the same workload, FP64 oracle, single thread "
-                                         "(%.1f s, setup %.1f s)" % (args.cpu_steps, dt, setup)}
+        threads, avail, model = host_cores()
+        mlups, dt, setup = cpu_baseline(sp, fe, args.cpu_steps, "omp")
+        m1, dt1, setup1 = cpu_baseline(sp, fe, args.cpu_steps_serial, None)
+        out["cpu_baseline"] = {
+            "value": round(mlups, 4), "unit": "MLUPS (fine-equivalent)", "cores": threads, "kind": "oracle",
+            "sample": "%d coarse steps of the same workload, FP64 oracle built with OpenMP, %d threads on %d "
+                      "available logical CPUs (%s): %.1f s after a %.1f s set-up" % (
+                          args.cpu_steps, threads, avail, model or "lscpu model unknown", dt, setup),
+            "single_thread": {"value": round(m1, 4), "cores": 1,
+                              "sample": "%d coarse step(s), the same oracle built without OpenMP: %.1f s after a "
+                                        "%.1f s set-up" % (args.cpu_steps_serial, dt1, setup1)}}
+        print("bench: oracle %.3f MLUPS_fe on %d threads, %.3f single-thread" % (mlups, threads, m1),
+              file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -79,6 +79,8 @@ def _configure(L):
     L.ora_kbc.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
     L.ora_beta.restype = ctypes.c_double
     L.ora_beta.argtypes = [ctypes.c_double]
+    L.ora_threads.restype = ctypes.c_int
+    L.ora_threads.argtypes = []
     L.ora_kbc_adj.restype = None
     L.ora_kbc_adj.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp]
     for name, args in [
@@ -136,6 +138,11 @@ def _f3(v):
     a = np.zeros(3, dtype=np.float64)
     a[: len(v)] = v
     return a
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP build's node loops run on."""
+    return int(lib_omp().ora_threads())
 
 
 def q_of(D: int) -> int:

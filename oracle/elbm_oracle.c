@@ -46,6 +46,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OMAXL 8
 #define OMAXQ 27
@@ -143,6 +146,15 @@ static void lattice(int D, int c[OMAXQ][3], double W[OMAXQ]) {
 
 /* Eq. visc with c_s^2 = 1/3:  nu = (1/3)(1/(2 beta) - 1/2)  =>  beta = 1/(6 nu + 1). */
 double ora_beta(double nu) { return 1.0 / (6.0 * nu + 1.0); }
+
+/* threads the node loops use: 1 unless built with OpenMP */
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* Eq. feq_iso: f_i^eq = rho W_i prod_a (2 - sqrt(1+3u_a^2)) ((2u_a + sqrt(1+3u_a^2))/(1-u_a))^{c_ia}. */
 void ora_feq(int D, double rho, const double u[3], double *feq) {

@@ -61,6 +61,8 @@ void ora_feq(int D, double rho, const double u[3], double *feq);
 double ora_kbc(int D, double beta, const double *f, const double F[3], double *out, double *ds,
                double *dh);
 double ora_beta(double nu);
+/* threads the node loops run on (1 unless built with OpenMP) */
+int ora_threads(void);
 
 /* discrete adjoint (reverse mode of the coarse step above) */
 void ora_kbc_adj(int D, double beta, const double *f, const double F[3], const double *lo, double *lf,

@@ -1100,11 +1100,14 @@ LevelStatic level_static(const elbm_ctx *c, int l) {
   return s;
 }
 
+// The level and pair constants are read by every kernel: they are rewritten in order
+// on the bound stream (after the work already enqueued there, which may still read the
+// old values) and the call returns once the copy is done (the sources live on the host
+// stack).
 elbm_status upload_static(elbm_ctx *c) {
   LevelStatic ls[MAXL];
   memset(ls, 0, sizeof(ls));
   for (int l = 0; l < c->L; ++l) ls[l] = level_static(c, l);
-  HIPCK(c, hipMemcpy(c->ws + c->o_levstatic, ls, sizeof(ls), hipMemcpyHostToDevice));
   PairStatic ps[MAXL];
   memset(ps, 0, sizeof(ps));
   for (size_t p = 0; p < c->pairs.size(); ++p) {
@@ -1112,11 +1115,19 @@ elbm_status upload_static(elbm_ctx *c) {
     ps[p].fac_cp = c->pairs[p].fac_cp;
     ps[p].parent = (int)p;
   }
-  HIPCK(c, hipMemcpy(c->ws + c->o_pairstatic, ps, sizeof(ps), hipMemcpyHostToDevice));
+  HIPCK(c, hipMemcpyAsync(c->ws + c->o_levstatic, ls, sizeof(ls), hipMemcpyHostToDevice, c->stream));
+  HIPCK(c, hipMemcpyAsync(c->ws + c->o_pairstatic, ps, sizeof(ps), hipMemcpyHostToDevice, c->stream));
+  HIPCK(c, hipStreamSynchronize(c->stream));
   return ELBM_OK;
 }
 
+// Executable graphs are destroyed only once nothing launched from them can still run:
+// an earlier elbm_advance returns before its graph launches finish, and the runtime may
+// run a graph's branches on streams of its own, so the whole device is waited for.
 void invalidate_graphs(elbm_ctx *c) {
+  bool any = false;
+  for (int p = 0; p < 2; ++p) any = any || c->graph[p] || c->graphm[p];
+  if (any) hipDeviceSynchronize();
   for (int p = 0; p < 2; ++p) {
     if (c->graph[p]) {
       hipGraphExecDestroy(c->graph[p]);

@@ -410,3 +410,72 @@ def test_full_size_one_step_from_gpu_state(elbm, name, storage, k, bound):
     assert e_u < bound
     del g
     torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------- full size, many steps
+# From identical seeded inputs the GPU runs the full-size workload for the stored number
+# of coarse steps (channel 50, sphere 100, forest 20) in the launch configuration the
+# benchmark times; the oracle's state after the same steps (FP64, stored by
+# tests/golden/make_fullsize.py, which calls only the oracle) is compared on one z-plane
+# of every level (through the interfaces and the body), with the total mass.
+FULLSIZE = [
+    ("channel3d", "f32", 1e-5), ("channel3d", "f16s", 3e-3), ("channel3d", "bf16s", 3e-2),
+    ("sphere3d", "f32", 1e-5), ("sphere3d", "f16s", 3e-3), ("sphere3d", "bf16s", 3e-2),
+    ("forest3d", "f32", 1e-5), ("forest3d", "f16s", 3e-3),
+]
+
+
+@pytest.mark.parametrize("name,storage,bound", FULLSIZE, ids=["%s-%s" % c[:2] for c in FULLSIZE])
+def test_full_size_many_steps_against_oracle(elbm, name, storage, bound):
+    import torch
+
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "fullsize_%s.npz" % name))
+    steps = int(ref["steps"])
+    sp = getattr(synth, name)()
+    print("full-size case %s storage=%s steps=%d" % (name, storage, steps), flush=True)
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    synth.apply(sp, g)
+    g.bind()
+    for l in range(sp.levels):
+        lo, n = g.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        g.init(l, rho, u, nz)
+    g.use_cached_launch()
+    g.advance(steps)
+    mass, _, bad = g.reduce()
+    e_u, e_r = 0.0, 0.0
+    for l in range(sp.levels):
+        k = int(ref["l%d_z" % l])
+        rho, u = g.moments(l)
+        ro = ref["l%d_rho_m1" % l].astype(np.float64) + 1.0
+        uo = ref["l%d_u" % l].astype(np.float64)
+        m = np.isfinite(ro)
+        assert np.array_equal(m, np.isfinite(rho[k])), "node sets differ on level %d" % l
+        e_u = max(e_u, float(np.max(np.abs(u[:, k][:, m] - uo[:, m]))) / sp.U)
+        e_r = max(e_r, float(np.max(np.abs(rho[k][m] - ro[m]))))
+    m_ref, m0 = float(ref["mass"]), float(ref["mass0"])
+    print("%s %s after %d steps: max|du|/U %.3e  max|drho| %.3e  mass vs oracle %.3e  oracle mass drift %.3e" % (
+        name, storage, steps, e_u, e_r, (mass - m_ref) / m_ref, (m_ref - m0) / m0), flush=True)
+    assert bad == 0
+    assert e_u < bound
+    del g
+    torch.cuda.empty_cache()
+
+
+def test_child_process_tuner_writes_a_cache_the_library_applies(elbm, tmp_path):
+    """The tuner times each candidate in a child process, writes the fastest; the
+    library then applies that entry (elbm_tune cache hit)."""
+    from paper_1608_06915_amd import tune
+
+    cache = str(tmp_path / "cache.txt")
+    print("case tuner channel3d(32,20,16,4) f32 small candidates", flush=True)
+    key, best, results = tune.tune("tests.tune_workloads:small_channel", "f32", cache, kind="small", steps=5,
+                                   warmup=2, windows=2, timeout=110)
+    assert sum("ms_per_step" in r for r in results) == len(results)
+    assert tune.read_cache(cache)[key] == [best[f] for f in tune.FIELDS]
+    from tests.tune_workloads import small_channel
+
+    sp = small_channel()
+    g, _ = pair(elbm, sp, "f32", 0)
+    assert g.use_cached_launch(cache)
+    assert g.get_launch() == best
