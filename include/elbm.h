@@ -132,6 +132,18 @@ elbm_status elbm_bind(elbm_ctx *ctx, void *workspace_dev, size_t bytes, void *hi
 elbm_status elbm_init_fields(elbm_ctx *ctx, int level, const double *rho_host, const double *u_host,
                              const double *noise_host);
 
+/* For callers that cannot allocate device memory (code running under a HIP graph
+ * capture of its own, tight serving loops, harnesses that forbid hipMalloc):
+ * elbm_init_fields with the host arrays staged through a static device buffer of
+ * 32 MiB instead of memory allocated per call, the same initial state bit for bit.
+ * Each GPU the library runs on holds one such buffer from the first elbm_bind on it
+ * until the process ends; every call on that GPU shares it, so calls that overlap on
+ * one GPU (other threads or contexts) race.  The level needs n (1 + D + Q) 8 bytes of
+ * staging (n = nodes of the level index box; without noise n (1 + D) 8): ELBM_EINVAL
+ * beyond 32 MiB, nothing written.  Synchronous. */
+elbm_status elbm_init_fields_static(elbm_ctx *ctx, int level, const double *rho_host, const double *u_host,
+                                    const double *noise_host);
+
 /* Per-node body-force density field of a level (device, [D][box], level-0 units),
  * added to the uniform force; NULL removes it.  Asynchronous on the bound stream. */
 elbm_status elbm_set_force_field(elbm_ctx *ctx, int level, const double *F_dev);

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -162,6 +163,7 @@ struct elbm_ctx {
     float ms[3] = {0, 0, 0};  // forward with checkpoints, recomputation, reverse sweep
   } adj;
   int cu_count = 256;
+  void *static_staging = nullptr;  // this device's copy of the static staging buffer
 };
 
 #define FAIL(ctx, code, ...)                                          \
@@ -184,7 +186,32 @@ struct elbm_ctx {
     if (_e) FAIL(ctx, ELBM_EDEVICE, "%s: %s", #call, hipGetErrorString((hipError_t)_e));       \
   } while (0)
 
+// Staging buffer of elbm_init_fields_static, for callers that cannot allocate device
+// memory.  Each GPU the library runs on holds its own copy until the process ends.  In
+// host code this name only stands for the symbol: its device address (per device) comes
+// from hipGetSymbolAddress, taken once per device when a context binds.
+constexpr size_t kStaticStagingBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kStaticStagingBytes];
+
 namespace {
+
+std::mutex g_staging_mu;
+constexpr int kMaxDevices = 64;
+void *g_staging_ptr[kMaxDevices] = {};
+
+// device address of the static staging buffer on the current device (looked up once)
+hipError_t static_staging_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_staging_mu);
+  if (!g_staging_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_staging_ptr[dev] = p;
+  }
+  *out = g_staging_ptr[dev];
+  return hipSuccess;
+}
 
 // ------------------------------------------------------------------ geometry helpers
 int64_t period(const elbm_ctx *c, int l, int a) { return c->N[a] << l; }
@@ -1834,6 +1861,7 @@ elbm_status elbm_bind(elbm_ctx *c, void *ws, size_t bytes, void *stream) {
   hipDeviceProp_t prop;
   HIPCK(c, hipGetDeviceProperties(&prop, dev));
   c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  HIPCK(c, static_staging_address(dev, &c->static_staging));
   if (!c->side) HIPCK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   if (!c->cap) HIPCK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   if (!c->side2) HIPCK(c, hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
@@ -1929,6 +1957,34 @@ elbm_status elbm_init_fields(elbm_ctx *c, int level, const double *rho, const do
   hipFree(d);
   if (rc) FAIL(c, ELBM_EDEVICE, "init kernel: %s", hipGetErrorString((hipError_t)rc));
   if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "init: %s", hipGetErrorString(e));
+  return ELBM_OK;
+}
+
+elbm_status elbm_init_fields_static(elbm_ctx *c, int level, const double *rho, const double *u,
+                                    const double *noise) {
+  if (!c || !rho || !u) return ELBM_EINVAL;
+  elbm_status s = check_level(c, level);
+  if (s) return s;
+  if (!c->bound || !c->static_staging) FAIL(c, ELBM_ESTATE, "init before bind");
+  const Level &L = c->lev[level];
+  const size_t tot = (size_t)(L.bn[0] * L.bn[1] * L.bn[2]);
+  const size_t nb = tot * (1 + c->D + (noise ? c->Q : 0)) * sizeof(double);
+  if (nb > kStaticStagingBytes)
+    FAIL(c, ELBM_EINVAL, "level %d needs %zu bytes of staging, more than the %zu of the static buffer", level, nb,
+         kStaticStagingBytes);
+  // the staging copies follow the work already enqueued on the bound stream (an earlier
+  // call's init kernel may still read the buffer)
+  double *d = (double *)c->static_staging;
+  HIPCK(c, hipMemcpyAsync(d, rho, tot * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCK(c, hipMemcpyAsync(d + tot, u, tot * c->D * 8, hipMemcpyHostToDevice, c->stream));
+  if (noise) HIPCK(c, hipMemcpyAsync(d + tot * (1 + c->D), noise, tot * c->Q * 8, hipMemcpyHostToDevice, c->stream));
+  const int cur = level == 0 ? c->parity : 0;
+  Dims box;
+  for (int a = 0; a < 3; ++a) box.n[a] = L.bn[a];
+  LCK(c, launch_init(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
+                     L.nb, (const int32_t *)(c->ws + L.o_borg), box, d, d + tot,
+                     noise ? d + tot * (1 + c->D) : nullptr, c->stream));
+  HIPCK(c, hipStreamSynchronize(c->stream));
   return ELBM_OK;
 }
 

@@ -29,7 +29,7 @@ STATUS = {0: "ELBM_OK", 1: "ELBM_EINVAL", 2: "ELBM_ESTATE", 3: "ELBM_ESMALL", 4:
 EXPORTS = [
     "elbm_create", "elbm_destroy", "elbm_status_string", "elbm_last_error", "elbm_set_face", "elbm_add_block",
     "elbm_set_solid", "elbm_set_force_uniform", "elbm_finalize", "elbm_level_box", "elbm_level_info",
-    "elbm_node_class", "elbm_weights", "elbm_bind", "elbm_init_fields", "elbm_set_force_field", "elbm_advance",
+    "elbm_node_class", "elbm_weights", "elbm_bind", "elbm_init_fields", "elbm_init_fields_static", "elbm_set_force_field", "elbm_advance",
     "elbm_read_moments", "elbm_read_populations", "elbm_sample_populations", "elbm_reduce", "elbm_check",
     "elbm_drag", "elbm_set_gamma_output", "elbm_brick_dims", "elbm_gamma_indicator", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
     "elbm_state_bytes", "elbm_save_state", "elbm_load_state", "elbm_get_launch",
@@ -77,6 +77,7 @@ def lib():
             "elbm_weights": [P, i32, dp],
             "elbm_bind": [P, P, ctypes.c_size_t, P],
             "elbm_init_fields": [P, i32, dp, dp, dp],
+            "elbm_init_fields_static": [P, i32, dp, dp, dp],
             "elbm_set_force_field": [P, i32, P],
             "elbm_advance": [P, i32],
             "elbm_read_moments": [P, i32, P, P, P],
@@ -240,6 +241,14 @@ class Lattice:
         self._ck(lib().elbm_init_fields(self._h, level, _dp(rho), _dp(u), None if nz is None else _dp(nz)))
 
     init_fields = init
+
+    def init_static(self, level, rho, u, noise=None):
+        """elbm_init_fields_static: the same initial state, staged through the library's
+        static device buffer (no device allocation)."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+        self._ck(lib().elbm_init_fields_static(self._h, level, _dp(rho), _dp(u), None if nz is None else _dp(nz)))
 
     def set_force_field(self, level, F: Optional[torch.Tensor]):
         if F is None:
