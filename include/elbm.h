@@ -256,8 +256,9 @@ elbm_status elbm_load_state(elbm_ctx *ctx, const void *dev_src);
 typedef enum { ELBM_OBJ_DRAG = 0, ELBM_OBJ_KE = 1 } elbm_objective;
 
 /* Device workspace for runs of up to n_max coarse steps with a checkpoint every K
- * coarse steps: ceil(n_max/K) checkpointed states, a tape of K 2^l + 1 states per
- * level l for the recomputed segment, and the adjoint fields.  After elbm_finalize. */
+ * coarse steps: ceil(n_max/K) checkpointed states, two tapes of K 2^l + 1 states per
+ * level l (the recomputation of one segment fills one while the reverse sweep of the
+ * next segment reads the other), and the adjoint fields.  After elbm_finalize. */
 elbm_status elbm_adjoint_bytes(elbm_ctx *ctx, int n_max, int K, size_t *bytes);
 /* Bind the caller-owned adjoint workspace (256-byte aligned, at least the size above;
  * never freed by the library).  After elbm_bind. */
@@ -283,9 +284,11 @@ elbm_status elbm_adjoint_read(elbm_ctx *ctx, int level, double *lam_dev, double 
  * Synchronous. */
 elbm_status elbm_adjoint_velocity(elbm_ctx *ctx, int level, const double *rho_host, const double *u_host,
                                   const double *noise_host, double *out_host);
-/* Milliseconds of the last adjoint run: forward with checkpoints, recomputation,
- * reverse ticks. */
-elbm_status elbm_adjoint_timing(const elbm_ctx *ctx, double ms[3]);
+/* Milliseconds of the last adjoint run: [0] forward with checkpoints, [1] recomputation
+ * (summed over segments), [2] reverse ticks (summed), [3] the whole backward pass
+ * (the recomputation of a segment overlaps the reverse sweep of the next one, so
+ * [3] < [1] + [2] when there are several segments). */
+elbm_status elbm_adjoint_timing(const elbm_ctx *ctx, double ms[4]);
 
 #ifdef __cplusplus
 }

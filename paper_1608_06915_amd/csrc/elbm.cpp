@@ -27,9 +27,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -142,9 +144,12 @@ struct elbm_ctx {
     bool bound = false, pending = false;
     char *ws = nullptr;
     int nmax = 0, K = 1;
-    size_t o_tape[MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL] = {}, o_lF[MAXL] = {},
+    // two tapes (and two staged-row tapes): the recomputation of one segment fills one
+    // while the reverse sweep of the next segment reads the other
+    size_t o_tape[2][MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL] = {}, o_lF[MAXL] = {},
            o_amask[MAXL] = {}, o_alev = 0, o_astage = 0, o_tofs = 0, o_tsten = 0, o_items = 0, o_part = 0,
-           o_res = 0, o_stape = 0, need = 0;
+           o_res = 0, o_stape[2] = {}, need = 0;
+    int rset = 0;  // tape set the reverse sweep reads
     // staged rows of every coupling tick of a segment, kept from the recomputation for
     // the reverse sweep: slot of tick t (-1 without coupling), slots per coarse step,
     // bytes per slot
@@ -160,7 +165,7 @@ struct elbm_ctx {
     int cur[MAXL] = {};  // lam buffer holding the adjoint of the current state
     int n = 0, objective = 0, body_level = -1;
     double dir[3] = {0, 0, 0}, J = 0;
-    float ms[3] = {0, 0, 0};  // forward with checkpoints, recomputation, reverse sweep
+    float ms[4] = {0, 0, 0, 0};  // forward with checkpoints, recomputation, reverse sweep, whole backward pass
   } adj;
   int cu_count = 256;
   void *static_staging = nullptr;  // this device's copy of the static staging buffer
@@ -1467,7 +1472,7 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
   const size_t tb = comp_bytes(c->storage);
   size_t state = 0;
   for (int l = 0; l < c->L; ++l) {
-    A.o_tape[l] = take(level_state_bytes(c, l) * ((size_t)K * ((size_t)1 << l) + 1));
+    for (int q = 0; q < 2; ++q) A.o_tape[q][l] = take(level_state_bytes(c, l) * ((size_t)K * ((size_t)1 << l) + 1));
     state += level_state_bytes(c, l);
   }
   const size_t S = (size_t)((nmax + K - 1) / K);
@@ -1488,7 +1493,7 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
   for (int t = 1; t <= T; ++t)
     if (c->ticks[(size_t)t - 1].tile_n + c->ticks[(size_t)t - 1].ring_n > 0) A.ctick[(size_t)t - 1] = A.nct++;
   A.stage_bytes = align_up((size_t)stage_row_width(c->D) * std::max(c->stage_cols, 1) * tb, 256);
-  A.o_stape = take((size_t)K * A.nct * A.stage_bytes);
+  for (int q = 0; q < 2; ++q) A.o_stape[q] = take((size_t)K * A.nct * A.stage_bytes);
   A.o_tofs = take(A.tofs.size() * 4);
   A.o_tsten = take(A.tsten.size() * sizeof(StencilEntry));
   A.o_items = take(A.items.size() * sizeof(WorkItem));
@@ -1497,14 +1502,14 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
   A.need = off;
 }
 
-// staged rows of coupling tick t of coarse step k (1-based) of the current segment
-char *adj_stage(elbm_ctx *c, int k, int t) {
+// staged rows of coupling tick t of coarse step k (1-based) of a segment, in tape set q
+char *adj_stage(elbm_ctx *c, int q, int k, int t) {
   auto &A = c->adj;
-  return A.ws + A.o_stape + ((size_t)(k - 1) * A.nct + (size_t)A.ctick[(size_t)t - 1]) * A.stage_bytes;
+  return A.ws + A.o_stape[q] + ((size_t)(k - 1) * A.nct + (size_t)A.ctick[(size_t)t - 1]) * A.stage_bytes;
 }
 
-char *adj_tape(elbm_ctx *c, int l, size_t slot) {
-  return c->adj.ws + c->adj.o_tape[l] + slot * level_state_bytes(c, l);
+char *adj_tape(elbm_ctx *c, int q, int l, size_t slot) {
+  return c->adj.ws + c->adj.o_tape[q][l] + slot * level_state_bytes(c, l);
 }
 
 char *adj_ckpt(elbm_ctx *c, int s, int l) {
@@ -1530,7 +1535,7 @@ elbm_status adj_tick(elbm_ctx *c, int k, int t) {
   }
   for (int l = tk.lmin; l < L; ++l) {
     const int m = t >> (L - 1 - l);
-    src[l] = adj_tape(c, l, ((size_t)(k - 1) << l) + (size_t)(m - 1));
+    src[l] = adj_tape(c, A.rset, l, ((size_t)(k - 1) << l) + (size_t)(m - 1));
     lamd[l] = A.ws + A.o_lam[l][A.cur[l]];
     lams[l] = A.ws + A.o_lam[l][A.cur[l] ^ 1];
   }
@@ -1568,7 +1573,7 @@ elbm_status adj_tick(elbm_ctx *c, int k, int t) {
     ca.c.n_ring = (int)tk.ring_n;
     ca.c.stride = stage_row_width(c->D);
     ca.c.sten = (const StencilEntry *)(c->ws + c->o_sten);
-    ca.c.stage = adj_stage(c, k, t);
+    ca.c.stage = adj_stage(c, A.rset, k, t);
     ca.c.lev = lev;
     ca.c.pairs = pairs;
     for (int l = 0; l < MAXL; ++l) {
@@ -2513,49 +2518,132 @@ elbm_status elbm_adjoint_forward(elbm_ctx *c, int n, int objective, int body_lev
   return ELBM_OK;
 }
 
+// Recompute segment s from its checkpoint into tape set s & 1 (every level substep's
+// state and the staged rows of every coupling tick), on stream st.
+elbm_status adj_recompute(elbm_ctx *c, int s, hipStream_t st) {
+  auto &A = c->adj;
+  const int T = 1 << (c->L - 1);
+  const int q = s & 1;
+  const int Ks = std::min(A.K, A.n - s * A.K);
+  for (int l = 0; l < c->L; ++l)
+    LCK(c, launch_copy(adj_tape(c, q, l, 0), adj_ckpt(c, s, l), level_state_bytes(c, l), st));
+  for (int k = 1; k <= Ks; ++k)
+    for (int t = 1; t <= T; ++t) {
+      void *src[MAXL] = {}, *dst[MAXL] = {};
+      for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) {
+        const size_t slot = ((size_t)(k - 1) << l) + (size_t)((t >> (c->L - 1 - l)) - 1);
+        src[l] = adj_tape(c, q, l, slot);
+        dst[l] = adj_tape(c, q, l, slot + 1);
+      }
+      elbm_status e = enqueue_tick_io(c, t, src, dst, st, c->side, false, 0,
+                                      A.ctick[(size_t)t - 1] >= 0 ? adj_stage(c, q, k, t) : nullptr);
+      if (e) return e;
+    }
+  return ELBM_OK;
+}
+
+// Segments are reversed from the last to the first.  The recomputation of segment s-1
+// (tape set (s-1) & 1, on a stream of its own) runs while the reverse sweep of segment s
+// reads set s & 1 on the bound stream; it waits for the reverse sweep of segment s+1,
+// the last reader of its set.  Every kernel of this workload is short, so the two
+// streams are fed by two host threads: a second thread enqueues the recomputations,
+// and each thread waits on the host until the other has recorded the event it depends
+// on before enqueueing the wait for it.
 elbm_status elbm_adjoint_backward(elbm_ctx *c) {
   if (!c) return ELBM_EINVAL;
   auto &A = c->adj;
   if (!A.bound || !A.pending) FAIL(c, ELBM_ESTATE, "adjoint_backward without a preceding adjoint_forward");
   const int T = 1 << (c->L - 1);
   const int S = (A.n + A.K - 1) / A.K;
-  std::vector<hipEvent_t> ev((size_t)3 * S);
+  hipStream_t R = c->side;  // idle outside graph capture and forked eager launches
+  // per segment: recompute start/end (stream R), reverse start/end (bound stream); and
+  // the start and end of the whole backward pass
+  std::vector<hipEvent_t> ev((size_t)4 * S + 2);
   for (auto &e : ev) HIPCK(c, hipEventCreate(&e));
-  elbm_status st = ELBM_OK;
-  for (int s = S - 1; s >= 0 && !st; --s) {
-    const int Ks = std::min(A.K, A.n - s * A.K);
-    for (int l = 0; l < c->L; ++l) LCK(c, launch_copy(adj_tape(c, l, 0), adj_ckpt(c, s, l), level_state_bytes(c, l), c->stream));
-    HIPCK(c, hipEventRecord(ev[(size_t)3 * s], c->stream));
-    for (int k = 1; k <= Ks && !st; ++k)
-      for (int t = 1; t <= T && !st; ++t) {
-        void *src[MAXL] = {}, *dst[MAXL] = {};
-        for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) {
-          const size_t slot = ((size_t)(k - 1) << l) + (size_t)((t >> (c->L - 1 - l)) - 1);
-          src[l] = adj_tape(c, l, slot);
-          dst[l] = adj_tape(c, l, slot + 1);
-        }
-        st = enqueue_tick_io(c, t, src, dst, c->stream, c->side, false, 0,
-                             A.ctick[(size_t)t - 1] >= 0 ? adj_stage(c, k, t) : nullptr);
+  auto E = [&](int s, int k) { return ev[(size_t)4 * s + k]; };
+  hipEvent_t e_begin = ev[(size_t)4 * S], e_end = ev[(size_t)4 * S + 1];
+  HIPCK(c, hipEventRecord(e_begin, c->stream));
+  std::mutex mu;
+  std::condition_variable cv;
+  int rec_done = S, rev_done = S;  // lowest segment whose end event each thread has recorded
+  bool stop = false;
+  elbm_status pst = ELBM_OK;
+  std::string perr;
+  std::thread producer([&]() {
+    hipError_t e = hipStreamWaitEvent(R, e_begin, 0);  // after everything before this call
+    for (int s = S - 1; s >= 0 && e == hipSuccess && !pst; --s) {
+      if (s + 2 < S) {  // set s & 1 is free once the reverse sweep of segment s + 2 has run
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || rev_done <= s + 2; });
+        if (stop) break;
+        lk.unlock();
+        e = hipStreamWaitEvent(R, E(s + 2, 3), 0);
+        if (e != hipSuccess) break;
       }
-    HIPCK(c, hipEventRecord(ev[(size_t)3 * s + 1], c->stream));
-    for (int k = Ks; k >= 1 && !st; --k)
+      e = hipEventRecord(E(s, 0), R);
+      if (e == hipSuccess) pst = adj_recompute(c, s, R);
+      if (e == hipSuccess && !pst) e = hipEventRecord(E(s, 1), R);
+      std::lock_guard<std::mutex> lk(mu);
+      if (e == hipSuccess && !pst) rec_done = s;
+      cv.notify_all();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (e != hipSuccess) {
+      pst = ELBM_EDEVICE;
+      perr = std::string("adjoint recomputation: ") + hipGetErrorString(e);
+    } else if (pst) {
+      perr = c->err;
+    }
+    if (pst) stop = true;
+    cv.notify_all();
+  });
+  elbm_status st = ELBM_OK;
+  hipError_t e = hipSuccess;
+  for (int s = S - 1; s >= 0 && !st && e == hipSuccess; --s) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || rec_done <= s; });
+      if (stop) break;
+    }
+    e = hipStreamWaitEvent(c->stream, E(s, 1), 0);
+    if (e == hipSuccess) e = hipEventRecord(E(s, 2), c->stream);
+    A.rset = s & 1;
+    const int Ks = std::min(A.K, A.n - s * A.K);
+    for (int k = Ks; k >= 1 && !st && e == hipSuccess; --k)
       for (int t = T; t >= 1 && !st; --t) st = adj_tick(c, k, t);
-    HIPCK(c, hipEventRecord(ev[(size_t)3 * s + 2], c->stream));
+    if (!st && e == hipSuccess) e = hipEventRecord(E(s, 3), c->stream);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!st && e == hipSuccess) rev_done = s;
+    cv.notify_all();
   }
-  HIPCK(c, hipStreamSynchronize(c->stream));
-  float rec = 0, rev = 0;
-  if (!st)
-    for (int s = 0; s < S; ++s) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (st || e != hipSuccess) stop = true;
+    cv.notify_all();
+  }
+  producer.join();
+  if (!st && e == hipSuccess && !pst) e = hipEventRecord(e_end, c->stream);
+  hipStreamSynchronize(R);
+  hipError_t se = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = se;
+  float rec = 0, rev = 0, tot = 0;
+  if (!st && !pst && e == hipSuccess) {
+    for (int s = 0; s < S && e == hipSuccess; ++s) {
       float a = 0, b = 0;
-      HIPCK(c, hipEventElapsedTime(&a, ev[(size_t)3 * s], ev[(size_t)3 * s + 1]));
-      HIPCK(c, hipEventElapsedTime(&b, ev[(size_t)3 * s + 1], ev[(size_t)3 * s + 2]));
+      e = hipEventElapsedTime(&a, E(s, 0), E(s, 1));
+      if (e == hipSuccess) e = hipEventElapsedTime(&b, E(s, 2), E(s, 3));
       rec += a;
       rev += b;
     }
-  for (auto &e : ev) hipEventDestroy(e);
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, e_begin, e_end);
+  }
+  for (auto &x : ev) hipEventDestroy(x);
   if (st) return st;
+  if (pst) FAIL(c, pst, "%s", perr.c_str());
+  if (e != hipSuccess) FAIL(c, ELBM_EDEVICE, "adjoint backward: %s", hipGetErrorString(e));
   A.ms[1] = rec;
   A.ms[2] = rev;
+  A.ms[3] = tot;
   A.pending = false;
   return ELBM_OK;
 }
@@ -2612,9 +2700,9 @@ elbm_status elbm_adjoint_velocity(elbm_ctx *c, int level, const double *rho, con
   return ELBM_OK;
 }
 
-elbm_status elbm_adjoint_timing(const elbm_ctx *c, double ms[3]) {
+elbm_status elbm_adjoint_timing(const elbm_ctx *c, double ms[4]) {
   if (!c || !ms) return ELBM_EINVAL;
-  for (int q = 0; q < 3; ++q) ms[q] = c->adj.ms[q];
+  for (int q = 0; q < 4; ++q) ms[q] = c->adj.ms[q];
   return ELBM_OK;
 }
 

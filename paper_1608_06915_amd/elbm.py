@@ -415,7 +415,8 @@ class Lattice:
         return out
 
     def adjoint_timing(self):
-        ms = np.zeros(3)
+        """(forward with checkpoints, recomputation, reverse sweep, whole backward pass) in ms"""
+        ms = np.zeros(4)
         self._ck(lib().elbm_adjoint_timing(self._h, _dp(ms)))
         return tuple(ms)
 

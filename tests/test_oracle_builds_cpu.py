@@ -47,13 +47,14 @@ def test_openmp_build_is_bitwise_the_single_thread_build(case):
         assert np.array_equal(a.drag(sp.body_level)[0], b.drag(sp.body_level)[0])
 
 
-@pytest.mark.parametrize("name", ["channel3d", "sphere3d", "forest3d"])
-def test_fullsize_references_match_the_workloads(name):
-    path = os.path.join(GOLDEN, "fullsize_%s.npz" % name)
+@pytest.mark.parametrize("name,steps", [("channel3d", 50), ("sphere3d", 25), ("sphere3d", 50), ("sphere3d", 100),
+                                        ("forest3d", 20)])
+def test_fullsize_references_match_the_workloads(name, steps):
+    path = os.path.join(GOLDEN, "fullsize_%s_%d.npz" % (name, steps))
     ref = np.load(path)
     sp = getattr(synth, name)()
     assert str(ref["workload"]) == name and int(ref["levels"]) == sp.levels
-    assert int(ref["steps"]) == {"channel3d": 50, "sphere3d": 100, "forest3d": 20}[name]
+    assert int(ref["steps"]) == steps
     o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels)
     synth.apply(sp, o)
     for l in range(sp.levels):
