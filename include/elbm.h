@@ -195,6 +195,23 @@ elbm_status elbm_brick_dims(int D, int64_t dims[3]);
  * the bound stream. */
 elbm_status elbm_gamma_indicator(elbm_ctx *ctx, int level, float *out_dev, int64_t grid[3]);
 
+/* Re-meshing: take over the current state of `src` in `dst`, a lattice of the same
+ * domain, levels, storage, viscosity, boundaries and forcing whose refinement blocks
+ * differ (the adaptive refinement the conclusion, Sec. V, proposes, e.g. driven by
+ * elbm_gamma_indicator).  Call at a coarse-step boundary, both lattices bound on the
+ * same device.  Per fluid node of dst: the stored values of src's node at the same
+ * level and position; else coalescence of src's node one level finer at the same
+ * position; else the four-point reconstruction of Eq. interp from src values at the
+ * parent positions (src nodes of the node's own level where present, src parent nodes
+ * elsewhere).  Density and velocity pass unchanged (or interpolated); the
+ * non-equilibrium part of the post-collision state scales by
+ * beta_c (1 - 2 beta_f) / (2 beta_f (1 - 2 beta_c)) from coarse to fine and by its
+ * inverse from fine to coarse (Eq. f_neq_rescaling_iso with f' - f^eq =
+ * (1 - 2 beta)(f - f^eq) at gamma = 2).  dst's drag accumulators restart.  ELBM_EINVAL
+ * if the lattices differ otherwise, or a dst node has no source (a newly refined
+ * region must lie where src has the parent level).  Synchronous; src is unchanged. */
+elbm_status elbm_transfer_state(elbm_ctx *dst, const elbm_ctx *src);
+
 /* Launch configuration: use_graph (0: eager launches; 1: one graph per coarse step;
  * G in 2..64: graphs of G coarse steps, single-step graphs for the remainder of an
  * elbm_advance), workgroups per CU
@@ -229,6 +246,15 @@ elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
  * Synchronous. */
 elbm_status elbm_profile(elbm_ctx *ctx, int steps, double *ms_total, double *ms_stream_collide,
                          int64_t *n_launches);
+/* Measurement aid, not part of the method: a plain streaming copy of `bytes` (a
+ * multiple of 16) from src_dev to dst_dev (caller-owned, 16-byte aligned, not
+ * overlapping) with `grid` workgroups of 256 threads (0: four per compute unit),
+ * 16-byte loads and non-temporal stores, on the given HIP stream (NULL: default).
+ * Timing it gives the read + write bandwidth HBM sustains for a pure stream, against
+ * which the stream-collide's traffic is compared.  ELBM_EINVAL for a bad argument.
+ * Asynchronous. */
+elbm_status elbm_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, int grid, void *hip_stream);
+
 /* Wait for the bound stream. */
 elbm_status elbm_synchronize(elbm_ctx *ctx);
 

@@ -69,6 +69,7 @@ def _configure(L):
         ("ora_reduce", [P, dp, dp]),
         ("ora_drag", [P, ctypes.c_int, dp, i64p, ctypes.c_int]),
         ("ora_couple_states", [P, ctypes.c_int, dp, dp]),
+        ("ora_transfer_state", [P, P]),
     ]:
         fn = getattr(L, name)
         fn.restype = ctypes.c_int
@@ -367,3 +368,8 @@ class Oracle:
         gc = np.array(g_child, dtype=np.float64, order="C", copy=True)
         self._ck(self._lib.ora_couple_states(self._h, int(parent_level), _dp(gp), _dp(gc)))
         return gp, gc
+
+    def transfer_from(self, src):
+        """Re-meshing: take over the state of another oracle lattice of the same domain,
+        levels and parameters with other refinement blocks (coarse-step boundary)."""
+        self._ck(self._lib.ora_transfer_state(self._h, src._h))

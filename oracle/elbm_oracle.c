@@ -1261,6 +1261,154 @@ int ora_drag(ora_t *o, int l, double F[3], int64_t *steps, int reset) {
 }
 
 /* ===========================================================================
+ * Re-meshing (adaptive refinement, proposed in Sec. V): the state of a lattice is
+ * carried over to another lattice of the same domain, levels and parameters whose
+ * refinement blocks differ, at a coarse-step boundary (every level holds a
+ * post-collision state at the same time instant).  Reading R15, per node of the new
+ * lattice:
+ *   1. the old lattice has a node at the same level and position: its populations;
+ *   2. else the old lattice has a node one level finer at the same position (the
+ *      region was refined and no longer is): coalescence of that node;
+ *   3. else (a newly refined region): reconstruction from the old lattice as in
+ *      Eq. interp, with the composite values of reading R7 (old nodes of the same level
+ *      where present, old parent nodes brought to the finer scale elsewhere).
+ * Density and velocity are carried over exactly (1) or by the four-point
+ * reconstruction (3); the non-equilibrium part of a post-collision state is
+ * f' - f^eq = (1 - 2 beta)(f - f^eq) for the LBGK value gamma = 2 of resolved flow
+ * (Eq. f_mirr), so Eq. f_neq_rescaling_iso becomes, for post-collision states, the
+ * factor beta_c (1 - 2 beta_f) / (2 beta_f (1 - 2 beta_c)) from coarse to fine and its
+ * inverse from fine to coarse.
+ * ------------------------------------------------------------------------- */
+
+/* rho, u and the non-equilibrium part of the stored post-collision state of node m */
+static void state_macro(const ora_t *o, int l, int64_t m, double *rho, double u[3], double *fneq) {
+  const olevel *L = &o->lev[l];
+  double r = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < o->Q; ++i) {
+    double f = L->f[(size_t)m * o->Q + i];
+    r += f;
+    for (int a = 0; a < 3; ++a) j[a] += o->c[i][a] * f;
+  }
+  for (int a = 0; a < 3; ++a) u[a] = j[a] / r;
+  *rho = r;
+  double feq[OMAXQ];
+  ora_feq(o->D, r, u, feq);
+  for (int i = 0; i < o->Q; ++i) fneq[i] = L->f[(size_t)m * o->Q + i] - feq[i];
+}
+
+/* post-collision non-equilibrium factor from level lc to level lc + 1 */
+static double post_factor(const ora_t *o, int lc) {
+  double bc = o->lev[lc].beta, bf = o->lev[lc + 1].beta;
+  return bc * (1.0 - 2.0 * bf) / (2.0 * bf * (1.0 - 2.0 * bc));
+}
+
+/* fluid node of the old lattice at level l, canonical position x; -1 if none */
+static int64_t old_node(const ora_t *s, int l, const int64_t xin[3]) {
+  int64_t x[3] = {xin[0], xin[1], xin[2]};
+  if (!canon(s, l, x)) return -1;
+  int64_t m = node_id(s, l, x);
+  if (m < 0 || s->lev[l].solid[m] || !s->lev[l].vf[m]) return -1;
+  return m;
+}
+
+int ora_transfer_state(ora_t *d, const ora_t *s) {
+  if (!d->finalized || !s->finalized) return fail(d, -2, "transfer before finalize");
+  if (d->D != s->D || d->L != s->L || d->nu0 != s->nu0) return fail(d, -1, "transfer: lattices differ");
+  for (int a = 0; a < 3; ++a)
+    if (d->N[a] != s->N[a] || d->periodic[a] != s->periodic[a] || d->Fu[a] != s->Fu[a])
+      return fail(d, -1, "transfer: domains differ");
+  for (int f = 0; f < 6; ++f)
+    if (d->face_kind[f] != s->face_kind[f]) return fail(d, -1, "transfer: boundaries differ");
+  int Q = d->Q, D = d->D;
+  static const double w4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
+  for (int l = 0; l < d->L; ++l) {
+    olevel *L = &d->lev[l];
+    for (int64_t n = 0; n < L->nn; ++n) {
+      L->vf[n] = 0;
+      if (L->solid[n]) continue;
+      const int64_t *x = &L->pos[3 * n];
+      double *out = &L->f[(size_t)n * Q];
+      int64_t xs[3] = {x[0], x[1], x[2]};
+      int64_t m = old_node(s, l, xs);
+      if (m >= 0) { /* 1. same node */
+        memcpy(out, &s->lev[l].f[(size_t)m * Q], sizeof(double) * Q);
+        L->gam[n] = s->lev[l].gam[m];
+        L->vf[n] = 1;
+        continue;
+      }
+      if (canon(s, l, xs)) {
+        int64_t k = node_id(s, l, xs);
+        if (k >= 0 && s->lev[l].solid[k]) return fail(d, -1, "transfer: level %d node solid in the old lattice only", l);
+      }
+      if (l + 1 < d->L) { /* 2. coalescence of the old finer node */
+        int64_t xc[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
+        int64_t mc = old_node(s, l + 1, xc);
+        if (mc >= 0) {
+          double r, u[3], fn[OMAXQ], feq[OMAXQ];
+          state_macro(s, l + 1, mc, &r, u, fn);
+          ora_feq(D, r, u, feq);
+          double fac = 1.0 / post_factor(s, l);
+          for (int i = 0; i < Q; ++i) out[i] = feq[i] + fac * fn[i];
+          L->gam[n] = 2.0;
+          L->vf[n] = 1;
+          continue;
+        }
+      }
+      if (l == 0) return fail(d, -1, "transfer: no source for level 0 node");
+      /* 3. reconstruction (Eq. interp) from composite old values at parent positions */
+      int npt[3] = {1, 1, 1};
+      int64_t pts[3][4];
+      double wts[3][4];
+      for (int a = 0; a < 3; ++a) {
+        if (a < D && (x[a] & 1)) {
+          npt[a] = 4;
+          for (int k = 0; k < 4; ++k) {
+            pts[a][k] = (x[a] - 3 + 2 * k) / 2;
+            wts[a][k] = w4[k];
+          }
+        } else {
+          pts[a][0] = x[a] / 2;
+          wts[a][0] = 1.0;
+        }
+      }
+      double rr = 0, uu[3] = {0, 0, 0}, nn_[OMAXQ];
+      for (int i = 0; i < Q; ++i) nn_[i] = 0.0;
+      for (int kz = 0; kz < npt[2]; ++kz)
+        for (int ky = 0; ky < npt[1]; ++ky)
+          for (int kx = 0; kx < npt[0]; ++kx) {
+            int64_t X[3] = {pts[0][kx], pts[1][ky], pts[2][kz]};
+            double w = wts[0][kx] * wts[1][ky] * wts[2][kz];
+            double r, u[3], fn[OMAXQ];
+            int64_t xf[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+            int64_t mf = old_node(s, l, xf);
+            if (mf >= 0) {
+              state_macro(s, l, mf, &r, u, fn);
+            } else {
+              int64_t mp = old_node(s, l - 1, X);
+              if (mp < 0)
+                return fail(d, -1, "transfer: level %d node (%lld,%lld,%lld) has no source", l, (long long)x[0],
+                            (long long)x[1], (long long)x[2]);
+              state_macro(s, l - 1, mp, &r, u, fn);
+              double fac = post_factor(s, l - 1);
+              for (int i = 0; i < Q; ++i) fn[i] *= fac;
+            }
+            rr += w * r;
+            for (int a = 0; a < 3; ++a) uu[a] += w * u[a];
+            for (int i = 0; i < Q; ++i) nn_[i] += w * fn[i];
+          }
+      double feq[OMAXQ];
+      ora_feq(D, rr, uu, feq);
+      for (int i = 0; i < Q; ++i) out[i] = feq[i] + nn_[i];
+      L->gam[n] = 2.0;
+      L->vf[n] = 1;
+    }
+    L->drag[0] = L->drag[1] = L->drag[2] = 0.0;
+    L->drag_steps = 0;
+  }
+  return 0;
+}
+
+/* ===========================================================================
  * Discrete adjoint (reverse mode of the exact forward map above, FP64).
  * The paper has no adjoint; this is the transpose of the linearisation of the
  * discrete coarse step defined by Sec. II.A and Sec. III.C as implemented here.

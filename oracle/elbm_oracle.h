@@ -55,6 +55,9 @@ int ora_drag(ora_t *o, int level, double F[3], int64_t *steps, int reset);
 /* Sec. III.C steps 3-4 on given post-stream states of levels lp, lp+1 (dense [Q][box],
  * in/out; non-finite = missing population) */
 int ora_couple_states(ora_t *o, int lp, double *gp, double *gc);
+/* Re-meshing: carry the state of src (same domain, levels, parameters, boundaries;
+ * other refinement blocks) over to dst at a coarse-step boundary */
+int ora_transfer_state(ora_t *dst, const ora_t *src);
 
 /* node-level primitives */
 void ora_feq(int D, double rho, const double u[3], double *feq);

@@ -9,7 +9,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libelbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "adjoint.hip", "indicator.hip", "elbm.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "adjoint.hip", "indicator.hip", "remesh.hip", "elbm.cpp")]
 ARCH = os.environ.get("ELBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -38,6 +38,7 @@
 #include "../../include/elbm.h"
 #include "elbm_dev.hpp"
 #include "indicator.hpp"
+#include "remesh.hpp"
 
 using namespace elbm;
 
@@ -2062,6 +2063,187 @@ elbm_status elbm_read_moments(elbm_ctx *c, int level, double *rho, double *u, do
   LCK(c, launch_read(c->D, c->storage, c->ws + L.o_pop[cur], (const LevelStatic *)(c->ws + c->o_levstatic), level,
                      L.nb, (const int32_t *)(c->ws + L.o_borg), box, rho, u, gamma, nullptr, c->stream));
   return ELBM_OK;
+}
+
+// ---------------------------------------------------------------- re-meshing
+// Transfer of the current state onto a lattice with other refinement blocks (the
+// adaptive refinement the conclusion, Sec. V, proposes).  The host decides where every
+// node of the new lattice takes its state from; remesh.hip does the arithmetic.
+namespace {
+// post-collision non-equilibrium factor from level lc to level lc + 1
+double post_factor(const elbm_ctx *c, int lc) {
+  const double bc = c->lev[lc].beta, bf = c->lev[lc + 1].beta;
+  return bc * (1.0 - 2.0 * bf) / (2.0 * bf * (1.0 - 2.0 * bc));
+}
+// a fluid node of level l at position x, or brick -1
+NodeRef fluid_at(const elbm_ctx *c, int l, const int64_t x[3]) {
+  NodeRef r = locate(c, l, x);
+  if (r.brick >= 0 && c->lev[l].solid[(size_t)r.brick * BN + r.node]) r.brick = -2;
+  return r;
+}
+}  // namespace
+
+elbm_status elbm_transfer_state(elbm_ctx *d, const elbm_ctx *s) {
+  if (!d || !s || d == s) return ELBM_EINVAL;
+  if (!d->bound || !s->bound) FAIL(d, ELBM_ESTATE, "transfer between lattices that are not both bound");
+  bool same = d->D == s->D && d->storage == s->storage && d->L == s->L && d->nu0 == s->nu0;
+  for (int a = 0; a < 3; ++a) same = same && d->N[a] == s->N[a] && d->periodic[a] == s->periodic[a] && d->Fu[a] == s->Fu[a];
+  for (int f = 0; f < 6; ++f) {
+    same = same && d->face_kind[f] == s->face_kind[f];
+    for (int a = 0; a < 3; ++a) same = same && d->face_u[f][a] == s->face_u[f][a];
+  }
+  if (!same) FAIL(d, ELBM_EINVAL, "transfer: the lattices differ in domain, levels, storage, parameters or boundaries");
+  std::vector<TPoint> pts;
+  std::unordered_map<int64_t, int32_t> pidx;
+  std::vector<TItem> items;
+  std::vector<StencilEntry> sten;
+  auto point = [&](int level, NodeRef r, double fac, int parent) -> int32_t {
+    const int64_t key = ((int64_t)(level * 2 + parent) << 48) | ((int64_t)r.brick << 8) | (int64_t)r.node;
+    auto it = pidx.find(key);
+    if (it != pidx.end()) return it->second;
+    TPoint p;
+    p.brick = r.brick;
+    p.node = (uint16_t)r.node;
+    p.level = (uint8_t)level;
+    p.pad = 0;
+    p.fac = fac;
+    pts.push_back(p);
+    pidx.emplace(key, (int32_t)pts.size() - 1);
+    return (int32_t)pts.size() - 1;
+  };
+  static const float w4[4] = {-1.0f / 16.0f, 9.0f / 16.0f, 9.0f / 16.0f, -1.0f / 16.0f};
+  for (int l = 0; l < d->L; ++l) {
+    const Level &L = d->lev[l];
+    for (int32_t b = 0; b < L.nb; ++b)
+      for (int n = 0; n < BN; ++n) {
+        const size_t k = (size_t)b * BN + n;
+        if (!L.exists[k] || L.solid[k]) continue;
+        int64_t x[3] = {0, 0, 0};
+        int rem = n;
+        for (int a = 0; a < 3; ++a) {
+          const int bd = bdim(d->D, a);
+          x[a] = L.blo[a] + L.borg[(size_t)b * 3 + a] + rem % bd;
+          rem /= bd;
+        }
+        TItem it;
+        it.brick = b;
+        it.node = (uint16_t)n;
+        it.level = (uint8_t)l;
+        NodeRef r = fluid_at(s, l, x);
+        if (r.brick == -2) FAIL(d, ELBM_EINVAL, "transfer: a level %d fluid node is solid in the old lattice", l);
+        if (r.brick >= 0) {
+          it.kind = 0;
+          it.a = r.brick;
+          it.b = r.node;
+          items.push_back(it);
+          continue;
+        }
+        if (l + 1 < d->L) {
+          const int64_t xc[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
+          NodeRef rc = fluid_at(s, l + 1, xc);
+          if (rc.brick >= 0) {
+            it.kind = 1;
+            it.a = rc.brick;
+            it.b = rc.node;
+            items.push_back(it);
+            continue;
+          }
+        }
+        if (l == 0) FAIL(d, ELBM_EINVAL, "transfer: no old value for a level 0 node");
+        // four-point reconstruction over the axes where x is not on a parent node
+        int npt[3] = {1, 1, 1};
+        int64_t P[3][4];
+        float W[3][4];
+        for (int a = 0; a < 3; ++a) {
+          if (a < d->D && (x[a] & 1)) {
+            npt[a] = 4;
+            for (int q = 0; q < 4; ++q) {
+              P[a][q] = (x[a] - 3 + 2 * q) / 2;
+              W[a][q] = w4[q];
+            }
+          } else {
+            P[a][0] = x[a] / 2;
+            W[a][0] = 1.0f;
+          }
+        }
+        it.kind = 2;
+        it.a = (int32_t)sten.size();
+        for (int kz = 0; kz < npt[2]; ++kz)
+          for (int ky = 0; ky < npt[1]; ++ky)
+            for (int kx = 0; kx < npt[0]; ++kx) {
+              const int64_t X[3] = {P[0][kx], P[1][ky], P[2][kz]};
+              const int64_t xf[3] = {2 * X[0], 2 * X[1], 2 * X[2]};
+              NodeRef rf = fluid_at(s, l, xf);
+              int32_t slot;
+              if (rf.brick >= 0) {
+                slot = point(l, rf, 1.0, 0);
+              } else {
+                NodeRef rp = fluid_at(s, l - 1, X);
+                if (rp.brick < 0)
+                  FAIL(d, ELBM_EINVAL, "transfer: level %d node (%lld,%lld,%lld) has no old value to reconstruct from", l,
+                       (long long)x[0], (long long)x[1], (long long)x[2]);
+                slot = point(l - 1, rp, post_factor(s, l - 1), 1);
+              }
+              StencilEntry e;
+              e.slot = slot;
+              e.w = W[0][kx] * W[1][ky] * W[2][kz];
+              sten.push_back(e);
+            }
+        it.b = (int32_t)sten.size() - it.a;
+        items.push_back(it);
+      }
+  }
+  // device copies of the tables and the staged rows (a transfer is rare: allocated
+  // here and released before returning)
+  const size_t row_bytes = (size_t)stage_row_width(d->D) * comp_bytes(d->storage);
+  const size_t o_pts = 0, o_items = align_up(o_pts + pts.size() * sizeof(TPoint) + 1, 256),
+               o_sten = align_up(o_items + items.size() * sizeof(TItem) + 1, 256),
+               o_stage = align_up(o_sten + sten.size() * sizeof(StencilEntry) + 1, 256),
+               total = o_stage + std::max<size_t>(pts.size(), 1) * row_bytes;
+  HIPCK(d, hipStreamSynchronize(s->stream));  // the old state is complete
+  char *buf = nullptr;
+  HIPCK(d, hipMalloc((void **)&buf, total));
+  hipError_t e = hipSuccess;
+  if (!pts.empty()) e = hipMemcpy(buf + o_pts, pts.data(), pts.size() * sizeof(TPoint), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(buf + o_items, items.data(), items.size() * sizeof(TItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !sten.empty())
+    e = hipMemcpy(buf + o_sten, sten.data(), sten.size() * sizeof(StencilEntry), hipMemcpyHostToDevice);
+  TransferArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pts = (const TPoint *)(buf + o_pts);
+  a.n_pts = (int)pts.size();
+  a.items = (const TItem *)(buf + o_items);
+  a.n_items = (int)items.size();
+  a.sten = (const StencilEntry *)(buf + o_sten);
+  a.stage = buf + o_stage;
+  for (int l = 0; l < d->L; ++l) {
+    a.src[l] = s->ws + s->lev[l].o_pop[l == 0 ? s->parity : 0];
+    a.dst[l] = d->ws + d->lev[l].o_pop[l == 0 ? d->parity : 0];
+    a.fac_coal[l] = l + 1 < d->L ? 1.0 / post_factor(s, l) : 1.0;
+  }
+  int rc = 0;
+  if (e == hipSuccess) rc = launch_transfer(d->D, d->storage, a, d->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+  hipFree(buf);
+  if (rc) FAIL(d, ELBM_EDEVICE, "transfer kernels: %s", hipGetErrorString((hipError_t)rc));
+  if (e != hipSuccess) FAIL(d, ELBM_EDEVICE, "transfer: %s", hipGetErrorString(e));
+  for (int l = 0; l < d->L; ++l) {
+    LCK(d, launch_zero(d->ws + d->lev[l].o_drag, (size_t)d->lev[l].nb * 3 * 8, d->stream));
+    d->drag_steps[l] = 0;
+  }
+  HIPCK(d, hipStreamSynchronize(d->stream));
+  return ELBM_OK;
+}
+
+elbm_status elbm_stream_copy(void *dst, const void *src, size_t bytes, int grid, void *stream) {
+  if (!dst || !src || (bytes & 15) || grid < 0) return ELBM_EINVAL;
+  if (grid == 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    grid = 4 * (cus > 0 ? cus : 256);
+  }
+  return launch_stream_copy(dst, src, bytes, grid, stream) ? ELBM_EDEVICE : ELBM_OK;
 }
 
 elbm_status elbm_brick_dims(int D, int64_t dims[3]) {

@@ -31,7 +31,7 @@ EXPORTS = [
     "elbm_set_solid", "elbm_set_force_uniform", "elbm_finalize", "elbm_level_box", "elbm_level_info",
     "elbm_node_class", "elbm_weights", "elbm_bind", "elbm_init_fields", "elbm_init_fields_static", "elbm_set_force_field", "elbm_advance",
     "elbm_read_moments", "elbm_read_populations", "elbm_sample_populations", "elbm_reduce", "elbm_check",
-    "elbm_drag", "elbm_set_gamma_output", "elbm_brick_dims", "elbm_gamma_indicator", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize",
+    "elbm_drag", "elbm_set_gamma_output", "elbm_brick_dims", "elbm_gamma_indicator", "elbm_transfer_state", "elbm_set_launch", "elbm_tune", "elbm_profile", "elbm_synchronize", "elbm_stream_copy",
     "elbm_state_bytes", "elbm_save_state", "elbm_load_state", "elbm_get_launch",
     "elbm_adjoint_bytes", "elbm_adjoint_bind", "elbm_adjoint_forward", "elbm_adjoint_backward",
     "elbm_adjoint_read", "elbm_adjoint_velocity", "elbm_adjoint_timing",
@@ -89,11 +89,13 @@ def lib():
             "elbm_set_gamma_output": [P, i32],
             "elbm_brick_dims": [i32, i64p],
             "elbm_gamma_indicator": [P, i32, P, i64p],
+            "elbm_transfer_state": [P, P],
             "elbm_set_launch": [P, i32, i32, i32, i32, i32, i32],
             "elbm_tune": [P, ctypes.c_char_p, i32],
             "elbm_get_launch": [P, P],
             "elbm_profile": [P, i32, dp, dp, i64p],
             "elbm_synchronize": [P],
+            "elbm_stream_copy": [P, P, ctypes.c_size_t, i32, P],
             "elbm_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
             "elbm_save_state": [P, P],
             "elbm_load_state": [P, P],
@@ -135,6 +137,18 @@ def _f3(v) -> np.ndarray:
 
 def _p64(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, grid: int = 0, stream=None) -> None:
+    """elbm_stream_copy: plain streaming copy of src into dst (device tensors of equal
+    byte size, a multiple of 16), on `stream` (default: the current torch stream)."""
+    nbytes = src.numel() * src.element_size()
+    assert src.is_cuda and dst.is_cuda and dst.numel() * dst.element_size() == nbytes
+    s = stream or torch.cuda.current_stream(src.device)
+    rc = lib().elbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, int(grid),
+                                ctypes.c_void_p(s.cuda_stream))
+    if rc:
+        raise ElbmError(rc, "elbm_stream_copy")
 
 
 class Lattice:
@@ -265,6 +279,17 @@ class Lattice:
     def synchronize(self):
         self._ck(lib().elbm_synchronize(self._h))
 
+    def moments_device(self, level):
+        """(rho, u) of a level as float64 device tensors over the level box (NaN at absent
+        and solid nodes), left on the device; asynchronous on the bound stream."""
+        sh = self.shape(level)
+        dev = self.workspace.device
+        rho = torch.empty(sh, dtype=torch.float64, device=dev)
+        u = torch.empty((self.D,) + sh, dtype=torch.float64, device=dev)
+        self._ck(lib().elbm_read_moments(self._h, level, ctypes.c_void_p(rho.data_ptr()),
+                                         ctypes.c_void_p(u.data_ptr()), None))
+        return rho, u
+
     def moments(self, level, gamma=False):
         sh = self.shape(level)
         dev = self.workspace.device
@@ -331,6 +356,12 @@ class Lattice:
         self._ck(lib().elbm_gamma_indicator(self._h, level, ctypes.c_void_p(out.data_ptr()), _p64(grid)))
         self.synchronize()
         return out.cpu().numpy().reshape(tuple(int(v) for v in grid[: self.D][::-1]))
+
+    def transfer_from(self, src: "Lattice"):
+        """Re-meshing: take over the current state of another bound lattice of the same
+        domain, levels and parameters with other refinement blocks (coarse-step
+        boundary)."""
+        self._ck(lib().elbm_transfer_state(self._h, src._h))
 
     def set_launch(self, use_graph=1, wg_per_cu=0, xcd_remap=1, threads=256, occupancy=1, pipeline=0):
         self._ck(lib().elbm_set_launch(self._h, int(use_graph), int(wg_per_cu), int(xcd_remap), int(threads),
