@@ -133,24 +133,33 @@ def owned_fine_equiv_updates(lat, sp):
 
 
 def copy_ceiling_gbs(mib=1024, reps=10):
-    """Read+write bandwidth of a plain device-to-device copy (the practical HBM ceiling)."""
+    """Read + write bandwidth of a plain streaming copy of `mib` MiB: the library's copy
+    kernel (16-byte accesses, non-temporal stores, four workgroups per compute unit) and
+    torch's copy_, each the median of three timings of `reps` copies."""
     import torch
+
+    from paper_1608_06915_amd import elbm
 
     n = (mib << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    e.synchronize()
-    gbs = 2 * (mib << 20) * reps / (s.elapsed_time(e) / 1e3) / 1e9
+    out = {}
+    for name, fn in (("stream_copy", lambda: elbm.stream_copy(b, a)), ("torch_copy", lambda: b.copy_(a))):
+        for _ in range(3):
+            fn()
+        t = []
+        for _ in range(3):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(reps):
+                fn()
+            e.record()
+            e.synchronize()
+            t.append(s.elapsed_time(e))
+        out[name] = 2 * (mib << 20) * reps / (float(np.median(t)) / 1e3) / 1e9
     del a, b
     torch.cuda.empty_cache()
-    return gbs
+    return out
 
 
 def run_gpu(sp, storage, steps, warmup, tune, launch=None, windows=5):
@@ -289,6 +298,115 @@ def run_adjoint(name, storage, n, K):
             "forward_MLUPS_fe": round(fe * n / (fwd_ms / 1e3) / 1e6, 1), "J": J, "launch": lat.get_launch()}
 
 
+def _plane_value(field, x, y):
+    """bilinear value of a 2-D plane field (numpy order y, x) at fractional (x, y), over the
+    corners that hold a value (NaN marks solid or absent nodes)"""
+    x0, y0 = int(math.floor(x)), int(math.floor(y))
+    acc, wsum = 0.0, 0.0
+    for dy in (0, 1):
+        for dx in (0, 1):
+            w = (1 - abs(x - (x0 + dx))) * (1 - abs(y - (y0 + dy)))
+            yy, xx = y0 + dy, x0 + dx
+            if 0 <= yy < field.shape[0] and 0 <= xx < field.shape[1] and np.isfinite(field[yy, xx]) and w > 0:
+                acc += w * field[yy, xx]
+                wsum += w
+    return acc / wsum if wsum > 0 else float("nan")
+
+
+def wake_statistics(lat, sp, steps, every):
+    """Time-averaged sphere-wake quantities over `steps` coarse steps, sampled every
+    `every` steps on the z-plane through the sphere centre (body level, the level above
+    it for the wake axis, level 0 for the free stream): the mean drag coefficient
+    C_d = F_x / (rho U^2 pi R^2 / 2); the base pressure coefficient C_pb = (p_b - p_inf) /
+    (rho U^2 / 2) with p = rho / 3, p_b at the first fluid node behind the sphere on the
+    axis and p_inf on the axis 5 D upstream; the recirculation length L_r / D from the
+    sphere's rear to where the mean axial velocity on the axis turns positive; the
+    separation angle, from the front stagnation point, where the mean tangential
+    velocity one node off the surface changes sign (both half-planes averaged)."""
+    import torch
+
+    bl = sp.body_level
+    cb, R = sp.bodies[bl][0], sp.body_diameter / 2.0
+    levels = sorted({0, max(bl - 1, 0), bl})
+    planes = {}
+    for l in levels:
+        lo, n = lat.level_box(l)
+        s = 2.0 ** (bl - l)
+        planes[l] = {"lo": lo, "k": int(round(cb[2] / s)) - int(lo[2]), "rho": None, "u": None}
+    lat.drag(bl, reset=True)
+    done, samples = 0, 0
+    while done < steps:
+        k = min(every, steps - done)
+        lat.advance(k)
+        done += k
+        for l in levels:
+            rho, u = lat.moments_device(l)
+            p = planes[l]
+            r2, u2 = rho[p["k"]].clone(), u[:, p["k"]].clone()
+            p["rho"] = r2 if p["rho"] is None else p["rho"] + r2
+            p["u"] = u2 if p["u"] is None else p["u"] + u2
+            del rho, u
+        samples += 1
+        if done % 1000 < every:
+            print("bench: wake averaging %d / %d coarse steps" % (done, steps), file=sys.stderr, flush=True)
+    F, nst = lat.drag(bl, reset=True)
+    lat.synchronize()
+    for l in levels:
+        planes[l]["rho"] = (planes[l]["rho"] / samples).cpu().numpy()
+        planes[l]["u"] = (planes[l]["u"] / samples).cpu().numpy()
+    U = sp.U
+    cd = 2.0 * (F[0] / nst) / (U ** 2 * math.pi * R * R)
+
+    def at(l, X, Y, what, comp=0):
+        """mean field of level l at body-level position (X, Y) on the plane"""
+        s = 2.0 ** (bl - l)
+        p = planes[l]
+        f = p["rho"] if what == "rho" else p["u"][comp]
+        return _plane_value(f, X / s - p["lo"][0], Y / s - p["lo"][1])
+
+    # free stream: level 0, 5 D upstream on the axis; base: first fluid node behind the sphere
+    D = 2.0 * R
+    rho_inf = at(0, cb[0] - 5 * D, cb[1], "rho")
+    xb = math.floor(cb[0] + R) + 1.0
+    rho_b = at(bl, xb, cb[1], "rho")
+    cpb = (rho_b - rho_inf) / 3.0 / (0.5 * rho_inf * U * U)
+    # recirculation length on the axis, finest level holding the point
+    lr = float("nan")
+    prev = None
+    X = xb
+    while X < cb[0] + 8 * D:
+        v = at(bl, X, cb[1], "u", 0)
+        if not np.isfinite(v) and bl > 0:
+            v = at(bl - 1, X, cb[1], "u", 0)
+        if not np.isfinite(v):
+            break
+        if prev is not None and prev[1] < 0.0 <= v:
+            x0 = prev[0] + (X - prev[0]) * (-prev[1]) / (v - prev[1])
+            lr = (x0 - (cb[0] + R)) / D
+            break
+        prev = (X, v)
+        X += 1.0
+    # separation angle one node off the surface, in both half-planes
+    angles = []
+    for sgn in (1.0, -1.0):
+        prev = None
+        for th in np.arange(20.0, 170.0, 0.25):
+            t = math.radians(th)
+            r = R + 1.0
+            Xp, Yp = cb[0] - r * math.cos(t), cb[1] + sgn * r * math.sin(t)
+            ut = at(bl, Xp, Yp, "u", 0) * math.sin(t) + at(bl, Xp, Yp, "u", 1) * sgn * math.cos(t)
+            if prev is not None and np.isfinite(ut) and np.isfinite(prev[1]) and prev[1] > 0.0 >= ut:
+                angles.append(prev[0] + (th - prev[0]) * prev[1] / (prev[1] - ut))
+                break
+            prev = (th, ut)
+    phis = float(np.mean(angles)) if angles else float("nan")
+    return {"C_d": round(float(cd), 5), "C_pb": round(float(cpb), 5), "L_r_over_D": round(float(lr), 4),
+            "phi_s_deg": round(phis, 3), "window_coarse_steps": steps, "samples": samples,
+            "paper": {"C_d": 0.383, "C_pb": -0.220, "L_r_over_D": 2.51, "phi_s_deg": 89.993},
+            "note": "halfway bounce-back walls (the paper uses Grad's wall condition); separation angle "
+                    "measured one node off the surface in the plane through the centre"}
+
+
 def cpu_baseline(sp, fe_updates, steps, library):
     """The FP64 oracle on the same workload: `steps` coarse steps after its set-up."""
     import oracle
@@ -348,6 +466,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--drag-steps", type=int, default=0,
                     help="after the timed steps, report the body's mean drag coefficient over this many coarse steps")
+    ap.add_argument("--wake-steps", type=int, default=0,
+                    help="after the drag window, time-average the sphere wake over this many coarse steps (C_d, C_pb, "
+                         "L_r, separation angle)")
+    ap.add_argument("--wake-every", type=int, default=10, help="coarse steps between wake samples")
     ap.add_argument("--adjoint-workload", default="cylinder2d")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
@@ -426,11 +548,18 @@ def main():
                        "stable": bool(lat.check())}
         print("bench: C_d %.4f over coarse steps %d-%d" % (cd, before, before + args.drag_steps),
               file=sys.stderr, flush=True)
+    if args.wake_steps > 0 and sp.body_level is not None and sp.D == 3:
+        out["wake"] = wake_statistics(lat, sp, args.wake_steps, args.wake_every)
+        out["wake"]["stable"] = bool(lat.check())
+        print("bench: wake " + json.dumps(out["wake"]), file=sys.stderr, flush=True)
     del lat
     torch.cuda.empty_cache()
     cc = copy_ceiling_gbs()
-    out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
-    print("bench: plain device copy %.0f GB/s (read + write)" % cc, file=sys.stderr, flush=True)
+    out["roofline"]["copy_ceiling_GBs"] = round(cc["stream_copy"], 1)
+    out["roofline"]["torch_copy_GBs"] = round(cc["torch_copy"], 1)
+    out["roofline"]["frac_of_copy_ceiling"] = round(out["roofline"]["achieved"] / cc["stream_copy"], 4)
+    print("bench: plain streaming copy %.0f GB/s read + write (torch copy_ %.0f GB/s); stream-collide at %.2f of it"
+          % (cc["stream_copy"], cc["torch_copy"], out["roofline"]["frac_of_copy_ceiling"]), file=sys.stderr, flush=True)
     if not args.no_half and args.storage == "f32" and not launch:
         lat2, half, _ = measure(args.workload, sp, "f16s", args.steps, args.warmup, not args.no_tune, None,
                                 args.windows)

@@ -222,6 +222,7 @@ int launch_init(int D, int st, void *pop, const LevelStatic *lev_dev, int level,
 int launch_read(int D, int st, const void *pop, const LevelStatic *lev_dev, int level, int nbricks,
                 const int32_t *borg, Dims box, double *rho, double *u, double *gamma, double *f, void *stream);
 int launch_fill_nan(double *p, size_t count, void *stream);
+int launch_stream_copy(void *dst, const void *src, size_t bytes, int grid, void *stream);
 int launch_sample(int D, int st, const void *pop, const LevelStatic *lev_dev, int level, int n,
                   const int32_t *bricks, const int32_t *nodes, double *out, void *stream);
 int launch_reduce(int D, int st, void *const *pops, const LevelStatic *lev_dev, const WorkItem *items, int n_items,

@@ -590,6 +590,21 @@ __global__ __launch_bounds__(256) void k_read(const typename Codec<ST>::S *pop, 
   if (gam) gam[k] = L.gamma ? (double)L.gamma[(size_t)b * BN + n] : 2.0;
 }
 
+// Plain streaming copy (16-byte loads, non-temporal 16-byte stores, grid-stride): the
+// read + write bandwidth HBM sustains for a pure stream, the practical ceiling the
+// stream-collide's traffic is compared against.
+__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                     size_t n) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += step) {
+    const float4 v = src[i];
+    const v4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (v4 *)&dst[i]);
+  }
+}
+
 __global__ void k_fill_nan(double *p, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t step = (size_t)gridDim.x * blockDim.x;
@@ -804,6 +819,13 @@ int launch_read(int D, int st, const void *pop, const LevelStatic *lev_dev, int 
   ELBM_DISPATCH(D, st,
                 (k_read<DD, SS><<<nbricks, BN, 0, (hipStream_t)stream>>>(
                     (const typename Codec<SS>::S *)pop, lev_dev, level, borg, box, rho, u, gamma, f)));
+  return ck();
+}
+
+int launch_stream_copy(void *dst, const void *src, size_t bytes, int grid, void *stream) {
+  const size_t n = bytes / 16;
+  if (!n) return 0;
+  k_stream_copy<<<grid, 256, 0, (hipStream_t)stream>>>((const float4 *)src, (float4 *)dst, n);
   return ck();
 }
 
