@@ -427,6 +427,131 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_transpose(
   }
 }
 
+// ---------------------------------------------------------------- 4 + 1 fused
+// The streaming transpose of one tick followed, node by node, by the collision adjoint
+// of the tick before it (in forward order): the transpose at node y needs only the
+// adjoint of the post-stream state at y's neighbours (lg of the later tick, read from
+// one buffer), and the collision adjoint at y needs only y's own transposed values, so
+// one launch does both and the lam a level collides with need not make a round trip
+// through memory before use (it is still stored: the coupling adjoint and the final
+// readout read it).  Per level: tpose bit -- the level's lg is transposed into lam;
+// coll bit -- the level's collision adjoint runs (on the transposed values when both
+// bits are set, else on the stored lam), writing the other lg buffer.
+template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_tc(AdjTCArgs a) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  using Bk = Brick<D>;
+  constexpr int Q = nq<D>();
+  WorkItem w = a.items[blockIdx.x];
+  w.brick = __builtin_amdgcn_readfirstlane(w.brick);
+  const int wl = __builtin_amdgcn_readfirstlane((int)w.level);
+  const int wthr = __builtin_amdgcn_readfirstlane((int)w.thr);
+  const bool tpose = (a.tpose_mask >> wl) & 1u, coll = (a.coll_mask >> wl) & 1u;
+  const LevelStatic &L = a.lev[wl];
+  const AdjLevel &AL = a.alev[wl];
+  const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
+  cptr<int32_t> nbc = cst(L.nbr) + (size_t)w.brick * 27;
+  __shared__ uint32_t s_nbo[27];
+  if (threadIdx.x < 27) {
+    const int nb = nbp[threadIdx.x];
+    s_nbo[threadIdx.x] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+  }
+  __syncthreads();
+  const T *__restrict__ lgb = (const T *)a.lgsrc[wl];
+  T *__restrict__ lam = (T *)a.lam[wl] + (size_t)w.brick * Q * BN;
+  T *__restrict__ lg = (T *)a.lgdst[wl] + (size_t)w.brick * Q * BN;
+  T *__restrict__ lF = a.lF[wl] ? (T *)a.lF[wl] + (size_t)w.brick * D * BN : nullptr;
+  const char *__restrict__ srcb = (const char *)a.src[wl];
+  auto boff = [&](int code) -> uint32_t {
+    const int nb = nbp[code];
+    return (uint32_t)(nb < 0 ? AL.zero_brick : nb) * (uint32_t)(Q * BN);
+  };
+  const uint32_t own = (uint32_t)w.brick * (uint32_t)(Q * BN);
+  const bool seed = wl == a.drag_level;
+  for (int n = threadIdx.x; n < BN; n += blockDim.x) {
+    const uint8_t cls = L.cls[(size_t)w.brick * BN + n];
+    const bool fluid = (cls & CLS_FLUID) != 0;
+    int x, y, z;
+    node_xyz<D>(n, x, y, z);
+    T l[Q];
+    if (tpose) {
+      if (fluid) {
+        const Lane<D> ln(x, y, z);
+        static_for<0, Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          constexpr int o = Q - 1 - i;  // position x + c_i = x - c_o
+          l[i] = lgb[boff(ln.code(o)) + (uint32_t)(i * BN + ln.local(o))];
+        });
+        if (cls & CLS_LINKS) {
+          const uint32_t mask = L.mask[(size_t)w.brick * BN + n];
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            if ((mask >> (Q - 1 - i)) & 1u) l[i] += lgb[own + (uint32_t)((Q - 1 - i) * BN + n)];
+        }
+        const uint32_t am = AL.amask ? AL.amask[(size_t)w.brick * BN + n] : 0u;
+        if (am) {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            if (!((am >> i) & 1u)) continue;
+            const int sx = x + cxo(i) + L.oshift[0], sy = y + cyo(i) + L.oshift[1],
+                      sz = z + czo<D>(i) + L.oshift[2];
+            const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
+            const int loc =
+                (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
+            l[i] += lgb[boff(code) + (uint32_t)(i * BN + loc)];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) l[i] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[i * BN + n] = l[i];
+    }
+    if (!coll) continue;
+    if (!fluid || (cls & CLS_MODE) < wthr) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lg[i * BN + n] = T(0);
+      continue;
+    }
+    if (!tpose) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) l[i] = lam[i * BN + n];
+    }
+    if (D == 3) z = __builtin_amdgcn_readfirstlane(z);
+    T h[Q];
+    uint32_t mask = 0;
+    {
+      uint32_t mid[9], side_[9];
+      bulk_offsets<D, ST>([&](int q) { return (int)nbc[q]; }, z, mid, side_);
+      const BulkLane<D> bl(x, y, z);
+      const Rsrc rs = buf_rsrc(srcb, (uint32_t)L.nbricks * brick_bytes<D, ST>());
+      const bool special = (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW)) != 0;
+      if (__builtin_amdgcn_ballot_w64(special) != 0) {
+        mask = special ? L.mask[(size_t)w.brick * BN + n] : 0u;
+        pull_links<D, ST>(rs, mid, side_, bl, [&](int q) { return s_nbo[q]; }, (uint32_t)w.brick * brick_bytes<D, ST>(),
+                          x, y, z, n, cls, mask, cst(a.lev) + wl, h);
+      } else {
+        pull_bulk<D, ST>(rs, mid, side_, bl, h);
+      }
+    }
+    if (seed && (cls & CLS_DRAG)) {  // d/df'_i of the mean momentum exchange 2 c_i f'_i
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if ((mask >> (Q - 1 - i)) & 1u)
+          l[i] += T(2.0 * (cxo(i) * a.drag_seed[0] + cyo(i) * a.drag_seed[1] + czo<D>(i) * a.drag_seed[2]));
+    }
+    T F[3], lFn[3];
+    node_force<D, T>(L, w.brick, n, F);
+    kbc_adjoint<D, T>(h, l, T(L.beta), F, lFn);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lg[i * BN + n] = l[i];
+    if (lF)
+#pragma unroll
+      for (int c = 0; c < D; ++c) lF[c * BN + n] += lFn[c] * T(L.fscale);
+  }
+}
+
 // ---------------------------------------------------------------- 2. coupling adjoint
 template <int D, int ST> __global__ __launch_bounds__(64) void k_adj_couple(AdjCoupleArgs A) {
   using C = Codec<ST>;
@@ -752,6 +877,12 @@ int launch_adj_collide(int D, int st, const AdjArgs &a, void *stream) {
 int launch_adj_transpose(int D, int st, const AdjArgs &a, void *stream) {
   if (a.n_items <= 0) return 0;
   ELBM_ADJ_DISPATCH(D, st, (k_adj_transpose<DD, SS><<<a.n_items, 256, 0, (hipStream_t)stream>>>(a)));
+  return ack();
+}
+
+int launch_adj_tc(int D, int st, const AdjTCArgs &a, void *stream) {
+  if (a.n_items <= 0) return 0;
+  ELBM_ADJ_DISPATCH(D, st, (k_adj_tc<DD, SS><<<a.n_items, 256, 0, (hipStream_t)stream>>>(a)));
   return ack();
 }
 

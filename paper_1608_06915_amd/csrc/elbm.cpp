@@ -147,9 +147,9 @@ struct elbm_ctx {
     int nmax = 0, K = 1;
     // two tapes (and two staged-row tapes): the recomputation of one segment fills one
     // while the reverse sweep of the next segment reads the other
-    size_t o_tape[2][MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL] = {}, o_lF[MAXL] = {},
+    size_t o_tape[2][MAXL] = {}, o_ckpt = 0, o_lam[MAXL][2] = {}, o_lg[MAXL][2] = {}, o_lF[MAXL] = {},
            o_amask[MAXL] = {}, o_alev = 0, o_astage = 0, o_tofs = 0, o_tsten = 0, o_items = 0, o_part = 0,
-           o_res = 0, o_stape[2] = {}, need = 0;
+           o_res = 0, o_stape[2] = {}, o_bitems = 0, need = 0;
     int rset = 0;  // tape set the reverse sweep reads
     // staged rows of every coupling tick of a segment, kept from the recomputation for
     // the reverse sweep: slot of tick t (-1 without coupling), slots per coarse step,
@@ -160,10 +160,16 @@ struct elbm_ctx {
     bool has_amask[MAXL] = {};
     std::vector<WorkItem> items;                  // every brick of the arriving levels, per tick
     std::vector<std::pair<size_t, size_t>> tick;  // (offset, count) into items per tick
+    // fused launches: after reversing tick t, the streaming transpose of t together with
+    // the collision adjoint of the tick before it (t - 1, or T of the previous coarse
+    // step): the bricks of the levels of either tick, thr of the colliding tick
+    std::vector<WorkItem> bitems;
+    std::vector<std::pair<size_t, size_t>> btick;
     std::vector<int32_t> tofs;
     std::vector<StencilEntry> tsten;
     std::vector<uint32_t> amask[MAXL];
     int cur[MAXL] = {};  // lam buffer holding the adjoint of the current state
+    int lgc[MAXL] = {};  // lg buffer holding the level's latest collision adjoint
     int n = 0, objective = 0, body_level = -1;
     double dir[3] = {0, 0, 0}, J = 0;
     float ms[4] = {0, 0, 0, 0};  // forward with checkpoints, recomputation, reverse sweep, whole backward pass
@@ -1403,6 +1409,24 @@ void adj_build_tables(elbm_ctx *c) {
       }
     A.tick.push_back({off, A.items.size() - off});
   }
+  A.bitems.clear();
+  A.btick.clear();
+  for (int t = 1; t <= T; ++t) {
+    const int tp = t > 1 ? t - 1 : T;
+    const int lt = c->ticks[t - 1].lmin, lp = c->ticks[tp - 1].lmin;
+    const size_t off = A.bitems.size();
+    for (int l = std::min(lt, lp); l < c->L; ++l)
+      for (int32_t b = 0; b < c->lev[l].nb; ++b) {
+        WorkItem w;
+        w.brick = b;
+        w.level = (uint8_t)l;
+        w.thr = (uint8_t)(l < lp ? 0 : ((l == lp && l > 0) ? 1 : 2));
+        w.drag = 0;
+        w.flags = 0;
+        A.bitems.push_back(w);
+      }
+    A.btick.push_back({off, A.bitems.size() - off});
+  }
   // transposed interpolation stencils: per staged row, the fine items reading it
   const int ncols = std::max(c->stage_cols, 1);
   std::vector<std::vector<StencilEntry>> by((size_t)ncols);
@@ -1482,7 +1506,8 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
     const size_t nb = (size_t)c->lev[l].nb;
     A.o_lam[l][0] = take(nb * c->Q * BN * tb);
     A.o_lam[l][1] = take(nb * c->Q * BN * tb);
-    A.o_lg[l] = take((nb + 1) * c->Q * BN * tb);
+    A.o_lg[l][0] = take((nb + 1) * c->Q * BN * tb);
+    A.o_lg[l][1] = take((nb + 1) * c->Q * BN * tb);
     A.o_lF[l] = take(nb * c->D * BN * tb);
     A.o_amask[l] = take(A.has_amask[l] ? nb * BN * 4 : 0);
   }
@@ -1498,6 +1523,7 @@ void adj_layout(elbm_ctx *c, int nmax, int K) {
   A.o_tofs = take(A.tofs.size() * 4);
   A.o_tsten = take(A.tsten.size() * sizeof(StencilEntry));
   A.o_items = take(A.items.size() * sizeof(WorkItem));
+  A.o_bitems = take(A.bitems.size() * sizeof(WorkItem));
   A.o_part = take(c->red_items.size() * 5 * 8);
   A.o_res = take(64);
   A.need = off;
@@ -1524,88 +1550,155 @@ char *adj_ckpt(elbm_ctx *c, int s, int l) {
 
 char *cur_state(elbm_ctx *c, int l) { return c->ws + c->lev[l].o_pop[l == 0 ? c->parity : 0]; }
 
-// reverse of tick t of coarse step k (1-based) of the current segment
-elbm_status adj_tick(elbm_ctx *c, int k, int t) {
+// Reverse sweep, tick by tick in reverse order.  Each level keeps two lam buffers (cur:
+// the adjoint of its current state) and two lg buffers (lgc: its latest collision
+// adjoint).  Reversing a tick t: (first tick of the run only) the collision adjoint;
+// the coupling and interpolation-point adjoints of t; then one fused launch with the
+// streaming transpose of t and the collision adjoint of the tick before it
+// (k_adj_tc), or the transpose alone after the first tick of the run.
+
+// tape slot of level l at tick t of coarse step k (1-based) of a segment
+size_t tape_slot(const elbm_ctx *c, int l, int k, int t) {
+  return ((size_t)(k - 1) << l) + (size_t)((t >> (c->L - 1 - l)) - 1);
+}
+
+void adj_fill_common(elbm_ctx *c, AdjArgs &a) {
   auto &A = c->adj;
-  const Tick &tk = c->ticks[t - 1];
-  const int L = c->L;
-  void *src[MAXL] = {}, *lamd[MAXL] = {}, *lams[MAXL] = {}, *lg[MAXL] = {}, *lF[MAXL] = {};
-  for (int l = 0; l < L; ++l) {
-    lg[l] = A.ws + A.o_lg[l];
-    lF[l] = A.ws + A.o_lF[l];
-  }
-  for (int l = tk.lmin; l < L; ++l) {
-    const int m = t >> (L - 1 - l);
-    src[l] = adj_tape(c, A.rset, l, ((size_t)(k - 1) << l) + (size_t)(m - 1));
-    lamd[l] = A.ws + A.o_lam[l][A.cur[l]];
-    lams[l] = A.ws + A.o_lam[l][A.cur[l] ^ 1];
-  }
-  const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
-  const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
-  AdjArgs a;
-  memset(&a, 0, sizeof(a));
-  a.items = (const WorkItem *)(A.ws + A.o_items) + A.tick[(size_t)t - 1].first;
-  a.n_items = (int)A.tick[(size_t)t - 1].second;
   a.drag_level = A.objective == ELBM_OBJ_DRAG ? A.body_level : -1;
   if (A.objective == ELBM_OBJ_DRAG) {
     const double nsub = (double)A.n * (double)((int64_t)1 << A.body_level);
     for (int q = 0; q < 3; ++q) a.drag_seed[q] = A.dir[q] / nsub;
   }
-  a.lev = lev;
+  a.lev = (const LevelStatic *)(c->ws + c->o_levstatic);
   a.alev = (const AdjLevel *)(A.ws + A.o_alev);
-  for (int l = 0; l < MAXL; ++l) {
-    a.src[l] = src[l];
-    a.lam[l] = lamd[l];
-    a.lg[l] = lg[l];
-    a.lF[l] = lF[l];
+}
+
+// collision adjoint of tick t of coarse step k (the first reversed tick of the run)
+elbm_status adj_collide_first(elbm_ctx *c, int k, int t) {
+  auto &A = c->adj;
+  AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  adj_fill_common(c, a);
+  a.items = (const WorkItem *)(A.ws + A.o_items) + A.tick[(size_t)t - 1].first;
+  a.n_items = (int)A.tick[(size_t)t - 1].second;
+  for (int l = 0; l < c->L; ++l) {
+    a.lg[l] = A.ws + A.o_lg[l][A.lgc[l]];
+    a.lF[l] = A.ws + A.o_lF[l];
+  }
+  for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) {
+    a.src[l] = adj_tape(c, A.rset, l, tape_slot(c, l, k, t));
+    a.lam[l] = A.ws + A.o_lam[l][A.cur[l]];
   }
   LCK(c, launch_adj_collide(c->D, c->storage, a, c->stream));
-  if (tk.tile_n + tk.ring_n > 0) {
-    // the staged rows of this tick were kept by the recomputation
-    AdjCoupleArgs ca;
-    memset(&ca, 0, sizeof(ca));
-    ca.c.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
-    ca.c.n_tiles = (int)tk.tile_n;
-    ca.c.lds_rows = c->lds_rows;
-    ca.c.lds_ents = c->lds_ents;
-    ca.c.tile_rows = (const int32_t *)(c->ws + c->o_trows);
-    ca.c.items = (const CItem *)(c->ws + c->o_fine);
-    ca.c.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;
-    ca.c.n_ring = (int)tk.ring_n;
-    ca.c.stride = stage_row_width(c->D);
-    ca.c.sten = (const StencilEntry *)(c->ws + c->o_sten);
-    ca.c.stage = adj_stage(c, A.rset, k, t);
-    ca.c.lev = lev;
-    ca.c.pairs = pairs;
-    for (int l = 0; l < MAXL; ++l) {
-      ca.c.src[l] = src[l];
-      ca.lam[l] = lamd[l];
-      ca.lg[l] = lg[l];
-      ca.lF[l] = lF[l];
-    }
-    ca.astage = A.ws + A.o_astage;
-    LCK(c, launch_adj_couple(c->D, c->storage, ca, c->stream));
-    // pairs one after the other: a level's points of two pairs may coincide
-    for (int p = tk.lmin; p + 1 < L; ++p) {
-      AdjPointArgs pa;
-      memset(&pa, 0, sizeof(pa));
-      pa.pts = (const GPoint *)(c->ws + c->o_gp) + c->pair_gp[(size_t)p].first;
-      pa.n = (int)c->pair_gp[(size_t)p].second;
-      pa.tofs = (const int32_t *)(A.ws + A.o_tofs);
-      pa.tsten = (const StencilEntry *)(A.ws + A.o_tsten);
-      pa.astage = A.ws + A.o_astage;
-      pa.lev = lev;
-      pa.pairs = pairs;
-      for (int l = 0; l < MAXL; ++l) {
-        pa.src[l] = src[l];
-        pa.lg[l] = lg[l];
-      }
-      LCK(c, launch_adj_points(c->D, c->storage, pa, c->stream));
+  return ELBM_OK;
+}
+
+// coupling and interpolation-point adjoints of tick t of coarse step k
+elbm_status adj_couple_part(elbm_ctx *c, int k, int t) {
+  auto &A = c->adj;
+  const Tick &tk = c->ticks[t - 1];
+  if (tk.tile_n + tk.ring_n == 0) return ELBM_OK;
+  const int L = c->L;
+  const LevelStatic *lev = (const LevelStatic *)(c->ws + c->o_levstatic);
+  const PairStatic *pairs = (const PairStatic *)(c->ws + c->o_pairstatic);
+  void *src[MAXL] = {};
+  for (int l = tk.lmin; l < L; ++l) src[l] = adj_tape(c, A.rset, l, tape_slot(c, l, k, t));
+  // the staged rows of this tick were kept by the recomputation
+  AdjCoupleArgs ca;
+  memset(&ca, 0, sizeof(ca));
+  ca.c.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;
+  ca.c.n_tiles = (int)tk.tile_n;
+  ca.c.lds_rows = c->lds_rows;
+  ca.c.lds_ents = c->lds_ents;
+  ca.c.tile_rows = (const int32_t *)(c->ws + c->o_trows);
+  ca.c.items = (const CItem *)(c->ws + c->o_fine);
+  ca.c.ring = (const CItem *)(c->ws + c->o_ring) + tk.ring_off;
+  ca.c.n_ring = (int)tk.ring_n;
+  ca.c.stride = stage_row_width(c->D);
+  ca.c.sten = (const StencilEntry *)(c->ws + c->o_sten);
+  ca.c.stage = adj_stage(c, A.rset, k, t);
+  ca.c.lev = lev;
+  ca.c.pairs = pairs;
+  for (int l = 0; l < MAXL; ++l) {
+    ca.c.src[l] = src[l];
+    if (l < L) {
+      ca.lam[l] = A.ws + A.o_lam[l][A.cur[l]];
+      ca.lg[l] = A.ws + A.o_lg[l][A.lgc[l]];
+      ca.lF[l] = A.ws + A.o_lF[l];
     }
   }
-  for (int l = 0; l < MAXL; ++l) a.lam[l] = lams[l];
+  ca.astage = A.ws + A.o_astage;
+  LCK(c, launch_adj_couple(c->D, c->storage, ca, c->stream));
+  // pairs one after the other: a level's points of two pairs may coincide
+  for (int p = tk.lmin; p + 1 < L; ++p) {
+    AdjPointArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.pts = (const GPoint *)(c->ws + c->o_gp) + c->pair_gp[(size_t)p].first;
+    pa.n = (int)c->pair_gp[(size_t)p].second;
+    pa.tofs = (const int32_t *)(A.ws + A.o_tofs);
+    pa.tsten = (const StencilEntry *)(A.ws + A.o_tsten);
+    pa.astage = A.ws + A.o_astage;
+    pa.lev = lev;
+    pa.pairs = pairs;
+    for (int l = 0; l < MAXL; ++l) {
+      pa.src[l] = src[l];
+      if (l < L) pa.lg[l] = A.ws + A.o_lg[l][A.lgc[l]];
+    }
+    LCK(c, launch_adj_points(c->D, c->storage, pa, c->stream));
+  }
+  return ELBM_OK;
+}
+
+// streaming transpose of tick t fused with the collision adjoint of the tick before it
+// (t - 1 of the same coarse step, or T of coarse step kp = k - 1), read from tape set q
+elbm_status adj_boundary(elbm_ctx *c, int t, int kp, int q) {
+  auto &A = c->adj;
+  const int T = 1 << (c->L - 1);
+  const int tp = t > 1 ? t - 1 : T;
+  const int lt = c->ticks[t - 1].lmin, lp = c->ticks[tp - 1].lmin;
+  AdjTCArgs a;
+  memset(&a, 0, sizeof(a));
+  a.items = (const WorkItem *)(A.ws + A.o_bitems) + A.btick[(size_t)t - 1].first;
+  a.n_items = (int)A.btick[(size_t)t - 1].second;
+  a.drag_level = A.objective == ELBM_OBJ_DRAG ? A.body_level : -1;
+  if (A.objective == ELBM_OBJ_DRAG) {
+    const double nsub = (double)A.n * (double)((int64_t)1 << A.body_level);
+    for (int d = 0; d < 3; ++d) a.drag_seed[d] = A.dir[d] / nsub;
+  }
+  a.lev = (const LevelStatic *)(c->ws + c->o_levstatic);
+  a.alev = (const AdjLevel *)(A.ws + A.o_alev);
+  for (int l = std::min(lt, lp); l < c->L; ++l) {
+    const bool tr = l >= lt, co = l >= lp;
+    if (tr) a.tpose_mask |= 1u << l;
+    if (co) a.coll_mask |= 1u << l;
+    a.lgsrc[l] = A.ws + A.o_lg[l][A.lgc[l]];
+    a.lam[l] = A.ws + A.o_lam[l][tr ? A.cur[l] ^ 1 : A.cur[l]];
+    a.lgdst[l] = A.ws + A.o_lg[l][A.lgc[l] ^ 1];
+    a.lF[l] = A.ws + A.o_lF[l];
+    if (co) a.src[l] = adj_tape(c, q, l, tape_slot(c, l, kp, tp));
+  }
+  LCK(c, launch_adj_tc(c->D, c->storage, a, c->stream));
+  for (int l = std::min(lt, lp); l < c->L; ++l) {
+    if (l >= lt) A.cur[l] ^= 1;
+    if (l >= lp) A.lgc[l] ^= 1;
+  }
+  return ELBM_OK;
+}
+
+// streaming transpose alone (the first tick of the run, reversed last)
+elbm_status adj_transpose_last(elbm_ctx *c, int t) {
+  auto &A = c->adj;
+  AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  adj_fill_common(c, a);
+  a.items = (const WorkItem *)(A.ws + A.o_items) + A.tick[(size_t)t - 1].first;
+  a.n_items = (int)A.tick[(size_t)t - 1].second;
+  for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) {
+    a.lg[l] = A.ws + A.o_lg[l][A.lgc[l]];
+    a.lam[l] = A.ws + A.o_lam[l][A.cur[l] ^ 1];
+  }
   LCK(c, launch_adj_transpose(c->D, c->storage, a, c->stream));
-  for (int l = tk.lmin; l < L; ++l) A.cur[l] ^= 1;
+  for (int l = c->ticks[t - 1].lmin; l < c->L; ++l) A.cur[l] ^= 1;
   return ELBM_OK;
 }
 
@@ -2613,7 +2706,8 @@ elbm_status elbm_adjoint_bind(elbm_ctx *c, void *ws, size_t bytes, int n_max, in
       al[l].amask = (const uint32_t *)(A.ws + A.o_amask[l]);
       HIPCK(c, hipMemcpy(A.ws + A.o_amask[l], A.amask[l].data(), A.amask[l].size() * 4, hipMemcpyHostToDevice));
     }
-    LCK(c, launch_zero(A.ws + A.o_lg[l], (nb + 1) * c->Q * BN * tb, c->stream));
+    LCK(c, launch_zero(A.ws + A.o_lg[l][0], (nb + 1) * c->Q * BN * tb, c->stream));
+    LCK(c, launch_zero(A.ws + A.o_lg[l][1], (nb + 1) * c->Q * BN * tb, c->stream));
     LCK(c, launch_zero(A.ws + A.o_lam[l][0], nb * c->Q * BN * tb, c->stream));
     LCK(c, launch_zero(A.ws + A.o_lam[l][1], nb * c->Q * BN * tb, c->stream));
     LCK(c, launch_zero(A.ws + A.o_lF[l], nb * c->D * BN * tb, c->stream));
@@ -2626,6 +2720,8 @@ elbm_status elbm_adjoint_bind(elbm_ctx *c, void *ws, size_t bytes, int n_max, in
                        hipMemcpyHostToDevice));
   if (!A.items.empty())
     HIPCK(c, hipMemcpy(A.ws + A.o_items, A.items.data(), A.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  if (!A.bitems.empty())
+    HIPCK(c, hipMemcpy(A.ws + A.o_bitems, A.bitems.data(), A.bitems.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   A.bound = true;
   return ELBM_OK;
 }
@@ -2693,7 +2789,7 @@ elbm_status elbm_adjoint_forward(elbm_ctx *c, int n, int objective, int body_lev
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   A.ms[0] = ms;
-  for (int l = 0; l < c->L; ++l) A.cur[l] = 0;
+  for (int l = 0; l < c->L; ++l) A.cur[l] = A.lgc[l] = 0;
   A.J = val;
   if (J) *J = val;
   A.pending = true;
@@ -2791,8 +2887,18 @@ elbm_status elbm_adjoint_backward(elbm_ctx *c) {
     if (e == hipSuccess) e = hipEventRecord(E(s, 2), c->stream);
     A.rset = s & 1;
     const int Ks = std::min(A.K, A.n - s * A.K);
+    // the transpose of the last reversed tick (coarse step 1, tick 1 of segment s + 1)
+    // with the collision adjoint of this segment's last tick, now recomputed
+    if (s + 1 < S && e == hipSuccess) st = adj_boundary(c, 1, Ks, s & 1);
     for (int k = Ks; k >= 1 && !st && e == hipSuccess; --k)
-      for (int t = T; t >= 1 && !st; --t) st = adj_tick(c, k, t);
+      for (int t = T; t >= 1 && !st; --t) {
+        if (s == S - 1 && k == Ks && t == T) st = adj_collide_first(c, k, t);
+        if (!st) st = adj_couple_part(c, k, t);
+        if (st) break;
+        if (t > 1) st = adj_boundary(c, t, k, s & 1);
+        else if (k > 1) st = adj_boundary(c, 1, k - 1, s & 1);
+        else if (s == 0) st = adj_transpose_last(c, 1);
+      }
     if (!st && e == hipSuccess) e = hipEventRecord(E(s, 3), c->stream);
     std::lock_guard<std::mutex> lk(mu);
     if (!st && e == hipSuccess) rev_done = s;

@@ -172,6 +172,21 @@ struct AdjArgs {  // collision adjoint and streaming transpose over whole bricks
   void *lF[MAXL];
 };
 
+struct AdjTCArgs {  // streaming transpose of one tick fused with the collision adjoint of the tick before
+  const WorkItem *items;  // every brick of the levels of either tick; thr of the colliding tick
+  int32_t n_items;
+  int32_t drag_level;
+  double drag_seed[3];
+  const LevelStatic *lev;
+  const AdjLevel *alev;
+  void *src[MAXL];    // forward state the colliding tick read (storage type)
+  void *lgsrc[MAXL];  // lg to transpose
+  void *lam[MAXL];    // written by the transpose (tpose levels), else read by the collision
+  void *lgdst[MAXL];  // lg written by the collision adjoint
+  void *lF[MAXL];
+  uint32_t tpose_mask, coll_mask;  // bit l: level l transposed / collided
+};
+
 struct AdjCoupleArgs {
   CoupleArgs c;     // tiles, items, ring, stencils, recomputed staged rows, src
   void *lam[MAXL];
@@ -237,6 +252,7 @@ int launch_zero(void *p, size_t bytes, void *stream);
 int launch_adj_collide(int D, int st, const AdjArgs &a, void *stream);
 int launch_adj_couple(int D, int st, const AdjCoupleArgs &a, void *stream);
 int launch_adj_points(int D, int st, const AdjPointArgs &a, void *stream);
+int launch_adj_tc(int D, int st, const AdjTCArgs &a, void *stream);
 int launch_adj_transpose(int D, int st, const AdjArgs &a, void *stream);
 int launch_adj_ke(int D, int st, const AdjKEArgs &a, double *result, void *stream);
 int launch_adj_read(int D, int st, const void *lam, const void *lF, const LevelStatic *lev_dev, int level,
