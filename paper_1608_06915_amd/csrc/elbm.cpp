@@ -1305,12 +1305,22 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     hipEvent_t e0, e1;
     HIPCK(c, hipEventCreate(&e0));
     HIPCK(c, hipEventCreate(&e1));
-    HIPCK(c, hipEventRecord(e0, main));
-    elbm_status st = run();
-    if (st) return st;
-    HIPCK(c, hipEventRecord(e1, main));
     c->tev.push_back(e0);
     c->tev.push_back(e1);
+    if (!split) {
+      // one launch: its dispatch packet stamps the events with the kernel's own start
+      // and end, as a kernel tracer reports it
+      cfg.ev0 = e0;
+      cfg.ev1 = e1;
+      elbm_status st = run();
+      cfg.ev0 = cfg.ev1 = nullptr;
+      if (st) return st;
+    } else {
+      HIPCK(c, hipEventRecord(e0, main));
+      elbm_status st = run();
+      if (st) return st;
+      HIPCK(c, hipEventRecord(e1, main));
+    }
   } else {
     elbm_status st = run();
     if (st) return st;

@@ -225,6 +225,9 @@ struct LaunchCfg {
   int threads;
   int occ;   // stream-collide register-budget variant: 1 uncapped, 4 capped at 128 VGPRs
   int pipe;  // 1: persistent software-pipelined stream-collide (grid = wg_per_cu x CUs)
+  // timing events (hipEvent_t) stamped with the kernel's own start and end by the
+  // dispatch packet (hipExtLaunchKernel), or null
+  void *ev0 = nullptr, *ev1 = nullptr;
 };
 int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *stream);
 int launch_gather(int D, int st, const GatherArgs &a, void *stream);

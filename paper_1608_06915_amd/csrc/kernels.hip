@@ -13,6 +13,8 @@
 // product of per-axis reciprocals (3 per axis instead of one per population).
 #include "lbm_device.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace elbm {
 
 // ---------------------------------------------------------------- stream-collide
@@ -744,27 +746,47 @@ static int ck() { return (int)hipGetLastError(); }
     }                                                         \
   } while (0)
 
+// One stream-collide launch; with timing events the dispatch packet stamps them with the
+// kernel's start and end (no host-side marker packets around the kernel).
+template <int D, int ST, int OCC, bool TWO, bool PLAIN>
+static void go_sc(int grid, int thr, const SCArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  if (cfg.ev0)
+    hipExtLaunchKernelGGL(k_stream_collide<D, ST, OCC, TWO, PLAIN>, dim3(grid), dim3(thr), 0, s,
+                          (hipEvent_t)cfg.ev0, (hipEvent_t)cfg.ev1, 0u, a);
+  else
+    k_stream_collide<D, ST, OCC, TWO, PLAIN><<<grid, thr, 0, s>>>(a);
+}
+
+template <int D, int ST> static void go_pipe(int grid, const SCArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  if (cfg.ev0)
+    hipExtLaunchKernelGGL(k_sc_pipe<D, ST>, dim3(grid), dim3(BN), 0, s, (hipEvent_t)cfg.ev0, (hipEvent_t)cfg.ev1, 0u,
+                          a);
+  else
+    k_sc_pipe<D, ST><<<grid, BN, 0, s>>>(a);
+}
+
 int launch_stream_collide(int D, int st, const SCArgs &a, LaunchCfg cfg, void *stream) {
   if (a.n_items <= 0) return 0;
   const int grid = cfg.grid > 0 ? cfg.grid : a.n_items;
   const int thr = cfg.threads > 0 ? cfg.threads : 256;
+  hipStream_t s = (hipStream_t)stream;
   if (cfg.pipe == 1) {  // persistent pipelined variant for plain bricks: one node per thread
-    ELBM_DISPATCH(D, st, (k_sc_pipe<DD, SS><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_pipe<DD, SS>(grid, a, cfg, s)));
     return ck();
   }
   if (cfg.pipe == 2) {  // plain bricks, one node per thread, at most 128 VGPRs
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, false, true><<<grid, BN, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_sc<DD, SS, 4, false, true>(grid, BN, a, cfg, s)));
     return ck();
   }
   const bool two = thr == BN / 2;
   if (cfg.occ >= 4 && two)
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, true><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_sc<DD, SS, 4, true, false>(grid, thr, a, cfg, s)));
   else if (cfg.occ >= 4)
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 4, false><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_sc<DD, SS, 4, false, false>(grid, thr, a, cfg, s)));
   else if (two)
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 1, true><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_sc<DD, SS, 1, true, false>(grid, thr, a, cfg, s)));
   else
-    ELBM_DISPATCH(D, st, (k_stream_collide<DD, SS, 1, false><<<grid, thr, 0, (hipStream_t)stream>>>(a)));
+    ELBM_DISPATCH(D, st, (go_sc<DD, SS, 1, false, false>(grid, thr, a, cfg, s)));
   return ck();
 }
 

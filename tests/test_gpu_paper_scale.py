@@ -1,0 +1,66 @@
+"""The sphere at the paper's own scale (Sec. IV: Re = 3700, D = 120 finest units, four
+levels, 89e6 nodes) checked against the oracle: after k coarse steps on the GPU, the
+GPU state of every level is loaded into the oracle (its OpenMP build) and both advance
+one more coarse step; every node's velocity and every population are compared.
+
+Several minutes of host work (the oracle's set-up and one step over 89e6 nodes) and
+about 60 GB of host memory: it runs only when ELBM_PAPER_SCALE=1 is set.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06915_amd import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("ELBM_PAPER_SCALE") != "1",
+                                 reason="paper-scale sphere: minutes of host oracle work; set ELBM_PAPER_SCALE=1")]
+
+
+@pytest.mark.timeout(1000)
+def test_paper_scale_sphere_one_step_from_gpu_state():
+    import torch
+
+    from paper_1608_06915_amd import elbm
+
+    sp = synth.sphere_paper3d()
+    print("paper-scale sphere: GPU set-up", flush=True)
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
+    synth.apply(sp, g)
+    g.bind()
+    for l in range(sp.levels):
+        lo, n = g.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        g.init(l, rho, u, nz)
+    g.set_launch(use_graph=10, wg_per_cu=0, xcd_remap=8, threads=256, occupancy=1, pipeline=0)
+    g.advance(20)
+    assert g.check()
+    print("paper-scale sphere: oracle set-up", flush=True)
+    o = oracle.Oracle(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, library="omp")
+    synth.apply(sp, o)
+    for l in range(sp.levels):
+        o.set_f(l, g.get_f(l))
+    print("paper-scale sphere: one coarse step on both", flush=True)
+    g.advance(1)
+    g.synchronize()
+    o.advance(1)
+    e_u, e_f = 0.0, 0.0
+    for l in range(sp.levels):
+        _, ug = g.moments(l)
+        _, uo, _ = o.moments(l)
+        m = np.isfinite(uo)
+        assert np.array_equal(m, np.isfinite(ug)), "node sets differ on level %d" % l
+        du = float(np.max(np.abs(ug[m] - uo[m]))) / sp.U
+        a, b = g.get_f(l), o.get_f(l)
+        mf = np.isfinite(b)
+        df = float(np.max(np.abs(a[mf] - b[mf])))
+        print("  level %d: %d nodes, max|du|/U %.3e, max|df| %.3e" % (l, int(m[0].sum()), du, df), flush=True)
+        e_u, e_f = max(e_u, du), max(e_f, df)
+        del a, b
+    print("paper-scale sphere, one step from the GPU state after 20: max|du|/U %.3e, max|df| %.3e" % (e_u, e_f),
+          flush=True)
+    assert e_u < 1e-5
+    del g
+    torch.cuda.empty_cache()
