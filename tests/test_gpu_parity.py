@@ -216,6 +216,30 @@ def test_launch_configurations_bitwise_equal(elbm, launch):
         assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
 
 
+@pytest.mark.parametrize("launch", [dict(use_graph=10, wg_per_cu=0, xcd_remap=8, threads=256),
+                                    dict(use_graph=1, wg_per_cu=0, xcd_remap=2, pipeline=2)],
+                         ids=["one-launch-per-tick", "split-ticks"])
+def test_profiling_pass_advances_like_advance(elbm, launch):
+    """elbm_profile times every stream-collide launch (a single launch through
+    hipExtLaunchKernel with start and stop events, a tick split into two launches between
+    recorded events) and advances the lattice exactly as elbm_advance does."""
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12))
+    g0, _ = pair(elbm, sp, "f32", 0, launch=launch)
+    g1, _ = pair(elbm, sp, "f32", 0, launch=launch)
+    g0.advance(3)
+    tot, sc, n = g1.profile(3)
+    g0.synchronize()
+    g1.synchronize()
+    assert n == 3 * (1 << (sp.levels - 1))
+    assert 0.0 < sc <= tot
+    for l in range(sp.levels):
+        assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
+    F0, s0 = g0.drag(2)
+    F1, s1 = g1.drag(2)
+    assert s0 == s1 and np.array_equal(F0, F1)
+
+
 # ----------------------------------------------------------------- FP32 workloads
 def test_channel_two_level_fp32(elbm):
     sp = synth.channel3d(32, 20, 16, 4, nu0=0.01)
