@@ -236,10 +236,10 @@ elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[6]);
  *   "key": [graph, wg_per_cu, xcd, threads, occupancy, pipeline]
  * line per workload shape, key = "d<dim>s<storage>_<bricks of level 0>_<bricks of
  * level 1>...".  On a hit the configuration is applied (as elbm_set_launch) and the
- * state is untouched.  On a miss the on-line search (timing `steps` coarse steps per
- * candidate, state restored, result appended to the cache) would run; it is switched
- * off in this version of the library and a miss returns ELBM_ESTATE with the key in the error text,
- * leaving the configuration unchanged. */
+ * state is untouched.  A miss (or a missing file) returns ELBM_ESTATE with the key in
+ * the error text and leaves the configuration unchanged.  The cache is written by the
+ * launch tuner (paper_1608_06915_amd/tune.py, every candidate timed in a process of its
+ * own); `steps` is reserved and ignored. */
 elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
 /* Time `steps` coarse steps with HIP events around every stream-collide launch;
  * returns the total and summed stream-collide milliseconds and launch count.

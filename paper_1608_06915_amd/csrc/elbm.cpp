@@ -2590,12 +2590,11 @@ elbm_status elbm_load_state(elbm_ctx *c, const void *src) {
   return ELBM_OK;
 }
 
-constexpr bool kOnlineSearch = false;
 
 elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
+  (void)steps;
   if (!c) return ELBM_EINVAL;
   if (!c->bound) FAIL(c, ELBM_ESTATE, "tune before bind");
-  if (steps < 1) steps = 1;
   // cache key: dimension, storage and bricks per level
   std::string key = "d" + std::to_string(c->D) + "s" + std::to_string(c->storage);
   for (int l = 0; l < c->L; ++l) key += "_" + std::to_string(c->lev[l].nb);
@@ -2614,70 +2613,11 @@ elbm_status elbm_tune(elbm_ctx *c, const char *cache_path, int steps) {
       fclose(f);
     }
   }
-  // The on-line search below is switched off: twice a process running it ended with a
-  // host segmentation fault inside this loop (which captures, instantiates and destroys
-  // two graphs per candidate, ~76 per call), and no cause in this library has been
-  // found (the host code is clean under AddressSanitizer with a stub runtime).  Until
-  // one is, only configurations from the cache are applied.
-  if (!kOnlineSearch)
-    FAIL(c, ELBM_ESTATE, "no cached launch configuration for %s (the on-line search is switched off)", key.c_str());
-  size_t sb = 0;
-  elbm_state_bytes(c, &sb);
-  void *save = nullptr;
-  HIPCK(c, hipMalloc(&save, sb));
-  elbm_status s = elbm_save_state(c, save);
-  const int par0 = c->parity;
-  struct Cand {
-    int w, x, t, o, p;
-  };
-  std::vector<Cand> cands;
-  for (int o : {1, 4})
-    for (int w : {0, 2, 4, 8})
-      for (int x : {0, 1})
-        for (int t : {256, 128}) cands.push_back({w, x, t, o, 0});
-  for (int w : {2, 3, 4})
-    for (int x : {0, 1}) cands.push_back({w, x, 256, 1, 1});
-  double best = 1e30;
-  Cand bc = {0, 1, 256, 1, 0};
-  hipEvent_t a = nullptr, b = nullptr;
-  if (!s && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-    for (const Cand &cd : cands) {
-      if ((s = elbm_set_launch(c, 1, cd.w, cd.x, cd.t, cd.o, cd.p))) break;
-      if ((s = elbm_advance(c, 1))) break;  // warm-up and graph build
-      hipEventRecord(a, c->stream);
-      if ((s = elbm_advance(c, steps))) break;
-      hipEventRecord(b, c->stream);
-      hipEventSynchronize(b);
-      float ms = 0;
-      hipEventElapsedTime(&ms, a, b);
-      if (ms < best) {
-        best = ms;
-        bc = cd;
-      }
-    }
-  }
-  if (a) hipEventDestroy(a);
-  if (b) hipEventDestroy(b);
-  // restore the state (parity first, so that the buffers line up)
-  c->parity = par0;
-  if (!s) s = elbm_load_state(c, save);
-  hipStreamSynchronize(c->stream);
-  hipFree(save);
-  if (s) return s;
-  s = elbm_set_launch(c, 1, bc.w, bc.x, bc.t, bc.o, bc.p);
-  if (s) return s;
-  for (int l = 0; l < c->L; ++l) {  // the timing runs advanced the drag accumulators
-    LCK(c, launch_zero(c->ws + c->lev[l].o_drag, (size_t)c->lev[l].nb * 3 * 8, c->stream));
-    c->drag_steps[l] = 0;
-  }
-  if (cache_path) {
-    FILE *f = fopen(cache_path, "a");
-    if (f) {
-      fprintf(f, "\"%s\": [%d, %d, %d, %d, %d, %d]\n", key.c_str(), 1, bc.w, bc.x, bc.t, bc.o, bc.p);
-      fclose(f);
-    }
-  }
-  return ELBM_OK;
+  // No search runs here: launch configurations are timed by paper_1608_06915_amd/tune.py,
+  // each candidate in a process of its own, which writes the cache read above.  (An
+  // in-process search that captured, instantiated and destroyed two graphs per candidate
+  // twice ended its process with a host segmentation fault whose cause was not found.)
+  FAIL(c, ELBM_ESTATE, "no cached launch configuration for %s", key.c_str());
 }
 
 
