@@ -389,18 +389,23 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
     // every global load of the tile is issued before the first barrier, none waiting on
     // another but the staged rows on their indices: the record of the node this lane
     // collides, the stencil ranges of its column tasks, the row indices and entries
-    CItem cn;
-    if (tid < t.nitem) cn = a.items[t.item0 + tid];
+    // (the loads are unconditional, with indices clamped into the tile -- a tile has at
+    // least one node, row and entry -- so that they are issued back to back; a load
+    // under its own condition is waited for inside that condition)
+    const CItem cn = a.items[t.item0 + (tid < t.nitem ? tid : 0)];
     int ea[TPT], eb[TPT];
 #pragma unroll
     for (int p = 0; p < TPT; ++p) {
       const int k = p * NT + tid;
-      ea[p] = eb[p] = 0;
-      if (k < ntask) {
-        const CItem c = a.items[t.item0 + k / NV];
-        ea[p] = c.a - t.e0;
-        eb[p] = c.b;
-      }
+      const CItem c = a.items[t.item0 + (k < ntask ? k : 0) / NV];
+      ea[p] = c.a;
+      eb[p] = c.b;
+    }
+#pragma unroll
+    for (int p = 0; p < TPT; ++p) {
+      const bool in = p * NT + tid < ntask;
+      ea[p] = in ? ea[p] - t.e0 : 0;
+      eb[p] = in ? eb[p] : 0;
     }
     constexpr int RC = 8;  // row columns and entries per lane per round
     for (int k0 = 0; k0 < nrow || k0 < t.ne; k0 += RC * NT) {
@@ -409,14 +414,14 @@ template <int D, int ST> __global__ __launch_bounds__(COUPLE_THREADS, ST == ST_F
 #pragma unroll
       for (int j = 0; j < RC; ++j) {
         const int k = k0 + j * NT + tid;
-        ri[j] = k < nrow ? a.tile_rows[t.pt0 + k / NV] : 0;
-        if (k < t.ne) se[j] = a.sten[t.e0 + k];
+        ri[j] = a.tile_rows[t.pt0 + (k < nrow ? k : 0) / NV];
+        se[j] = a.sten[t.e0 + (k < t.ne ? k : 0)];
       }
       V rv[RC];
 #pragma unroll
       for (int j = 0; j < RC; ++j) {
         const int k = k0 + j * NT + tid;
-        if (k < nrow) rv[j] = stage[(size_t)ri[j] * NV + k % NV];
+        rv[j] = stage[(size_t)ri[j] * NV + (k < nrow ? k : 0) % NV];
       }
 #pragma unroll
       for (int j = 0; j < RC; ++j) {
