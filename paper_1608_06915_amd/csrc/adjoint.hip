@@ -451,10 +451,15 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_tc(AdjTCAr
   const AdjLevel &AL = a.alev[wl];
   const int32_t *nbp = L.nbr + (size_t)w.brick * 27;
   cptr<int32_t> nbc = cst(L.nbr) + (size_t)w.brick * 27;
-  __shared__ uint32_t s_nbo[27];
+  // neighbour bricks: byte offsets of the populations (missing -> brick 0, masked by the
+  // pull) and element offsets of the adjoint buffer (missing -> the level's zero brick),
+  // looked up once per workgroup so that every load of a node's transpose is issued at
+  // once rather than after its own index load
+  __shared__ uint32_t s_nbo[27], s_nbl[27];
   if (threadIdx.x < 27) {
     const int nb = nbp[threadIdx.x];
     s_nbo[threadIdx.x] = (uint32_t)(nb < 0 ? 0 : nb) * brick_bytes<D, ST>();
+    s_nbl[threadIdx.x] = (uint32_t)(nb < 0 ? AL.zero_brick : nb) * (uint32_t)(Q * BN);
   }
   __syncthreads();
   const T *__restrict__ lgb = (const T *)a.lgsrc[wl];
@@ -462,10 +467,7 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_tc(AdjTCAr
   T *__restrict__ lg = (T *)a.lgdst[wl] + (size_t)w.brick * Q * BN;
   T *__restrict__ lF = a.lF[wl] ? (T *)a.lF[wl] + (size_t)w.brick * D * BN : nullptr;
   const char *__restrict__ srcb = (const char *)a.src[wl];
-  auto boff = [&](int code) -> uint32_t {
-    const int nb = nbp[code];
-    return (uint32_t)(nb < 0 ? AL.zero_brick : nb) * (uint32_t)(Q * BN);
-  };
+  auto boff = [&](int code) -> uint32_t { return s_nbl[code]; };
   const uint32_t own = (uint32_t)w.brick * (uint32_t)(Q * BN);
   const bool seed = wl == a.drag_level;
   for (int n = threadIdx.x; n < BN; n += blockDim.x) {
@@ -482,24 +484,32 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_adj_tc(AdjTCAr
           constexpr int o = Q - 1 - i;  // position x + c_i = x - c_o
           l[i] = lgb[boff(ln.code(o)) + (uint32_t)(i * BN + ln.local(o))];
         });
+        // special links: every load issued (own brick, or a valid neighbour), the
+        // terms taken under the link masks
         if (cls & CLS_LINKS) {
           const uint32_t mask = L.mask[(size_t)w.brick * BN + n];
+          T v[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) v[i] = lgb[own + (uint32_t)((Q - 1 - i) * BN + n)];
 #pragma unroll
           for (int i = 0; i < Q; ++i)
-            if ((mask >> (Q - 1 - i)) & 1u) l[i] += lgb[own + (uint32_t)((Q - 1 - i) * BN + n)];
+            if ((mask >> (Q - 1 - i)) & 1u) l[i] += v[i];
         }
         const uint32_t am = AL.amask ? AL.amask[(size_t)w.brick * BN + n] : 0u;
         if (am) {
+          T v[Q];
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
-            if (!((am >> i) & 1u)) continue;
             const int sx = x + cxo(i) + L.oshift[0], sy = y + cyo(i) + L.oshift[1],
                       sz = z + czo<D>(i) + L.oshift[2];
             const int code = side<Bk::BX>(sx) + 3 * side<Bk::BY>(sy) + 9 * (D == 3 ? side<Bk::BZ>(sz) : 1);
             const int loc =
                 (sx & (Bk::BX - 1)) + Bk::BX * ((sy & (Bk::BY - 1)) + Bk::BY * (D == 3 ? (sz & (Bk::BZ - 1)) : 0));
-            l[i] += lgb[boff(code) + (uint32_t)(i * BN + loc)];
+            v[i] = lgb[boff(code) + (uint32_t)(i * BN + loc)];
           }
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            if ((am >> i) & 1u) l[i] += v[i];
         }
       } else {
 #pragma unroll
@@ -569,13 +579,31 @@ template <int D, int ST> __global__ __launch_bounds__(64) void k_adj_couple(AdjC
     // weights are products of -1/16, 9/16 and 1: exact in FP16)
     constexpr int SL = lds_stride<D, T>();
     uint32_t *ents = (uint32_t *)(rows + (size_t)a.lds_rows * SL);
-    for (int k = threadIdx.x; k < t.npt * (SW / 4); k += blockDim.x) {
-      const int r = k / (SW / 4), q = k - r * (SW / 4);
-      ((V *)rows)[r * (SL / 4) + q] = stage[(size_t)a.tile_rows[t.pt0 + r] * (SW / 4) + q];
-    }
-    for (int k = threadIdx.x; k < t.ne; k += blockDim.x) {
-      const StencilEntry s = a.sten[t.e0 + k];
-      ents[k] = (uint32_t)s.slot | ((uint32_t)__half_as_ushort(__float2half_rn(s.w)) << 16);
+    // rows and entries in rounds of RC per lane, every load of a round issued at once
+    // (indices clamped into the tile, which has at least one row and one entry)
+    constexpr int NV = SW / 4, RC = 4;
+    const int nrow = t.npt * NV;
+    for (int k0 = 0; k0 < nrow || k0 < t.ne; k0 += RC * (int)blockDim.x) {
+      int ri[RC];
+      StencilEntry se[RC];
+      V rv[RC];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * (int)blockDim.x + (int)threadIdx.x;
+        ri[j] = a.tile_rows[t.pt0 + (k < nrow ? k : 0) / NV];
+        se[j] = a.sten[t.e0 + (k < t.ne ? k : 0)];
+      }
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * (int)blockDim.x + (int)threadIdx.x;
+        rv[j] = stage[(size_t)ri[j] * NV + (k < nrow ? k : 0) % NV];
+      }
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        const int k = k0 + j * (int)blockDim.x + (int)threadIdx.x;
+        if (k < nrow) ((V *)rows)[(k / NV) * (SL / 4) + k % NV] = rv[j];
+        if (k < t.ne) ents[k] = (uint32_t)se[j].slot | ((uint32_t)__half_as_ushort(__float2half_rn(se[j].w)) << 16);
+      }
     }
     __syncthreads();
     for (int it = threadIdx.x; it < t.nitem; it += blockDim.x) {
@@ -694,12 +722,24 @@ template <int D, int ST> __global__ __launch_bounds__(128) void k_adj_points(Adj
   T lrow[SW];
 #pragma unroll
   for (int v = 0; v < SW; ++v) lrow[v] = 0;
-  for (int e = a.tofs[g.slot]; e < a.tofs[g.slot + 1]; ++e) {
-    const StencilEntry s = a.tsten[e];
-    const T w = T(s.w);
-    const T *r = (const T *)a.astage + (size_t)s.slot * SW;
+  // the transposed stencil in rounds of four entries, their loads issued together (the
+  // index clamped to the last entry; an entry past the end adds with weight zero)
+  const int e0 = a.tofs[g.slot], e1 = a.tofs[g.slot + 1];
+  for (int e = e0; e < e1; e += 4) {
+    StencilEntry s[4];
 #pragma unroll
-    for (int v = 0; v < SW; ++v) lrow[v] = fma(w, r[v], lrow[v]);
+    for (int k = 0; k < 4; ++k) s[k] = a.tsten[e + k < e1 ? e + k : e1 - 1];
+    T r[4][SW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int v = 0; v < SW; ++v) r[k][v] = ((const T *)a.astage)[(size_t)s[k].slot * SW + v];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T w = e + k < e1 ? T(s[k].w) : T(0);
+#pragma unroll
+      for (int v = 0; v < SW; ++v) lrow[v] = fma(w, r[k][v], lrow[v]);
+    }
   }
   const LevelStatic &L = a.lev[g.level];
   const char *srcb = (const char *)a.src[g.level];
