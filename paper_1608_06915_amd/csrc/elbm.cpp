@@ -682,12 +682,13 @@ elbm_status build_level_links(elbm_ctx *c, int l) {
       if (mode > 0 || L.ring[k] || L.pd[k] <= 1) L.n_update++;
     }
     // plain bricks: every node fluid, stream-collided at this threshold, plain links only
-    bool plain1 = true, plain2 = true;
+    bool plain1 = true, plain2 = true, links = false;
     for (int n = 0; n < BN; ++n) {
       const uint8_t cl = L.cls[(size_t)b * BN + n];
       const bool ok = (cl & CLS_FLUID) && !(cl & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW | CLS_DRAG));
       plain1 = plain1 && ok && (cl & CLS_MODE) >= 1;
       plain2 = plain2 && ok && (cl & CLS_MODE) >= 2;
+      links = links || (cl & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW));
     }
     WorkItem w;
     w.brick = b;
@@ -696,12 +697,12 @@ elbm_status build_level_links(elbm_ctx *c, int l) {
     w.flags = 0;
     if (m1) {
       w.thr = 1;
-      w.flags = plain1 ? WI_PLAIN : 0;
+      w.flags = (uint8_t)((plain1 ? WI_PLAIN : 0) | (links ? WI_LINKS : 0));
       L.items1.push_back(w);
     }
     if (m2) {
       w.thr = 2;
-      w.flags = plain2 ? WI_PLAIN : 0;
+      w.flags = (uint8_t)((plain2 ? WI_PLAIN : 0) | (links ? WI_LINKS : 0));
       L.items2.push_back(w);
     }
     L.any_drag = L.any_drag || dr;

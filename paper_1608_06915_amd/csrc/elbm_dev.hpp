@@ -38,9 +38,10 @@ struct WorkItem {  // one brick of one level in a stream-collide launch
   uint8_t level;
   uint8_t thr;    // process nodes with mode >= thr
   uint8_t drag;   // brick holds drag nodes
-  uint8_t flags;  // WI_PLAIN: every node is fluid, has mode >= thr and only plain links
+  uint8_t flags;  // WI_PLAIN: every node is fluid, has mode >= thr and only plain links;
+                  // WI_LINKS: some node has bounce-back, inlet or outflow links
 };
-enum : uint8_t { WI_PLAIN = 1 };
+enum : uint8_t { WI_PLAIN = 1, WI_LINKS = 2 };
 static_assert(sizeof(WorkItem) == 8, "kernels read a WorkItem as one little-endian 64-bit word");
 
 struct ItemRec {  // stream-collide work item with its 27 neighbour bricks (one scalar fetch)

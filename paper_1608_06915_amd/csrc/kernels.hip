@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
     w.brick = (int32_t)(uint32_t)wi;
     const int wl = (int)((wi >> 32) & 0xff), wthr = (int)((wi >> 40) & 0xff), wdrag = (int)((wi >> 48) & 0xff);
     const bool plain = PLAIN || ((wi >> 56) & WI_PLAIN) != 0;
+    const bool links = !PLAIN && ((wi >> 56) & WI_LINKS) != 0;
     cptr<LevelStatic> Lc = cst(a.lev) + wl;
     cptr<int32_t> nbp = rec->nbr;
     const uint8_t *__restrict__ cls_p = Lc->cls + (size_t)w.brick * BN;
@@ -102,8 +103,12 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
     }
     for (int n = threadIdx.x; n < BN; n += blockDim.x) {
       uint8_t cls = CLS_FLUID | 2;
+      uint32_t lmask = 0;
       if (!plain) {
+        // in a brick with special links the node's link mask is loaded beside its class
+        // (not after it)
         cls = cls_p[n];
+        if (links) lmask = Lc->mask[(size_t)w.brick * BN + n];
         if ((cls & CLS_MODE) < wthr) continue;
       }
       int x, y, z;
@@ -115,7 +120,7 @@ __global__ __launch_bounds__(256, OCC) void k_stream_collide(SCArgs a) {
       // lanes have an empty mask there), so it runs one pull instead of two
       const bool special = !plain && (cls & (CLS_LINKS | CLS_INLET | CLS_OUTFLOW));
       if (!plain && __builtin_amdgcn_ballot_w64(special) != 0) {
-        mask = special ? Lc->mask[(size_t)w.brick * BN + n] : 0u;
+        mask = special ? lmask : 0u;
         uint32_t mid[9], side[9];
         bulk_offsets<D, ST>([&](int q) { return (int)nbp[q]; }, z, mid, side);
         const BulkLane<D> bl(x, y, z);
