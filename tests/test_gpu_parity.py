@@ -130,6 +130,41 @@ def test_sphere_three_level_fp64(elbm):
     assert np.max(np.abs(Fg - Fo)) < 1e-12 * np.max(np.abs(Fo))
 
 
+def ragged_sphere():
+    """The three-level sphere with a coarse domain of 40 nodes along the inlet/outflow
+    axis: 2.5 bricks of 16, so the last coarse brick is partly outside the domain."""
+    return synth.sphere3d(40, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                          centre=(20, 12, 12), noise=1e-3)
+
+
+def test_ragged_domain_fp64(elbm):
+    sp = ragged_sphere()
+    g, o = pair(elbm, sp, "f64", 6)
+    assert g.level_info(0)[3] == 3 * 6 * 6  # bricks of level 0: ceil(40 / 16) x 24 / 4 x 24 / 4
+    assert max_df(g, o, sp) < 1e-13
+
+
+@pytest.mark.parametrize("launch", [dict(use_graph=10, xcd_remap=8), dict(use_graph=1, wg_per_cu=2, xcd_remap=1),
+                                    dict(use_graph=0, xcd_remap=32, threads=128)],
+                         ids=["runs-8", "persistent-slabs", "eager-two-node"])
+def test_ragged_domain_launch_configurations_bitwise_equal(elbm, launch):
+    sp = ragged_sphere()
+    g0, _ = pair(elbm, sp, "f32", 5)
+    g1, _ = pair(elbm, sp, "f32", 5, launch=launch)
+    for l in range(sp.levels):
+        assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
+
+
+def test_advance_zero_steps_changes_nothing(elbm):
+    sp = ragged_sphere()
+    g, _ = pair(elbm, sp, "f32", 2)
+    f0 = [g.get_f(l) for l in range(sp.levels)]
+    g.advance(0)
+    g.synchronize()
+    for l in range(sp.levels):
+        assert np.array_equal(g.get_f(l), f0[l], equal_nan=True)
+
+
 def test_mass_momentum_and_gamma_fp64(elbm):
     sp = synth.tgv2d(32, (8, 24), 0.04, 0.02, noise=1e-3)
     g, o = pair(elbm, sp, "f64", 20, gamma=True)
