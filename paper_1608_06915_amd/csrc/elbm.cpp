@@ -1211,7 +1211,10 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     g.stage = stg;
     g.lev = lev;
     g.pairs = pairs;
-    for (int l = 0; l < MAXL; ++l) g.src[l] = src[l];
+    for (int l = 0; l < MAXL; ++l) {
+      g.src[l] = src[l];
+      g.nbr[l] = l < c->L ? (const int32_t *)(c->ws + c->lev[l].o_nbr) : nullptr;
+    }
     LCK(c, launch_gather(c->D, c->storage, g, cs));
     CoupleArgs a;
     a.tiles = (const CTile *)(c->ws + c->o_tiles) + tk.tile_off;

@@ -125,6 +125,7 @@ struct GatherArgs {
   const LevelStatic *lev;
   const PairStatic *pairs;
   void *src[MAXL];
+  const int32_t *nbr[MAXL];  // per level: the neighbour-brick table (as LevelStatic::nbr)
 };
 
 struct CoupleArgs {

@@ -284,9 +284,23 @@ template <int D, int ST> __global__ __launch_bounds__(256) void k_gather(GatherA
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n) return;
   const GPoint g = a.pts[p];
-  const LevelStatic &L = a.lev[g.level];
-  const char *srcb = (const char *)a.src[g.level];
-  const int32_t *nb = L.nbr + (size_t)g.brick * 27;
+  // the level's population buffer and neighbour table chosen among kernel arguments
+  // (selects, not a memory round trip on the lane's level)
+  // (the empty asm keeps each argument in scalar registers, so that the choice stays a
+  // select and is not turned back into an indexed load from the argument segment)
+  const char *srcb = nullptr;
+  const int32_t *nbt = nullptr;
+#pragma unroll
+  for (int l = 0; l < MAXL; ++l) {
+    const char *sl = (const char *)a.src[l];
+    const int32_t *nl = a.nbr[l];
+    asm volatile("" : "+s"(sl), "+s"(nl));
+    if (g.level == l) {
+      srcb = sl;
+      nbt = nl;
+    }
+  }
+  const int32_t *nb = nbt + (size_t)g.brick * 27;
   auto boff = [&](int code) { return (uint32_t)nb[code] * brick_bytes<D, ST>(); };
   int x, y, z;
   node_xyz<D>(g.node, x, y, z);
