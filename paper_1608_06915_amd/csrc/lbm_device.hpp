@@ -357,31 +357,35 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
   // entropic scalar products <ds|dh>, <dh|dh> with weight 1/f^eq_i.  The lattice
   // weights are products of the 1-D weights w(0) = 2/3, w(+-1) = 1/6, so
   // 1/f^eq_i = ir * prod_a 1/(w(c_a) (1 + a_a(c_a))): one reciprocal per axis and
-  // velocity component, the density folded into the last axis, one product per
-  // population.  The sums run as three fused multiply-add chains (by c_z; by c_y in 2-D).
+  // velocity component.  The sums run as three fused multiply-add chains, one per
+  // velocity component of the last axis (c_z; c_y in 2-D), whose factor 1/(w (1 + a))
+  // -- with the density folded in -- multiplies each chain's sum once at the end.
   T A = 0, B = 0;
   {
-    T r0[3], r1[3], r2[3] = {1, 1, 1};
+    T r0[3], r1[3], rl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const T w = k == 1 ? T(2.0 / 3.0) : T(1.0 / 6.0);
       r0[k] = rcp(fma(w, a[0][k], w));
-      r1[k] = rcp(fma(w, a[1][k], w));
-      if (D == 3) r2[k] = ir * rcp(fma(w, a[2][k], w));
-      else r1[k] *= ir;
+      if (D == 3) {
+        r1[k] = rcp(fma(w, a[1][k], w));
+        rl[k] = ir * rcp(fma(w, a[2][k], w));
+      } else {
+        r1[k] = T(1);
+        rl[k] = ir * rcp(fma(w, a[1][k], w));
+      }
     }
     T rxy[9];
 #pragma unroll
     for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) rxy[cx + 3 * cy] = r0[cx] * r1[cy];
+      for (int cx = 0; cx < 3; ++cx) rxy[cx + 3 * cy] = D == 3 ? r0[cx] * r1[cy] : r0[cx];
     T Ap[3] = {0, 0, 0}, Bp[3] = {0, 0, 0};
     static_for<0, Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int cx = cxo(i), cy = cyo(i), cz = czo<D>(i);
       constexpr int lane = D == 3 ? cz + 1 : cy + 1;
-      T ifq = rxy[(cx + 1) + 3 * (cy + 1)];
-      if (D == 3) ifq *= r2[cz + 1];
+      const T ifq = rxy[(cx + 1) + 3 * (cy + 1)];  // 1/f^eq_i without the last axis' factor
       const T ds = dsv(i);
       const T dh = h[i] - ds;
       const T t = dh * ifq;
@@ -389,8 +393,8 @@ __device__ inline T kbc_collide(T (&h)[nq<D>()], T beta, const T F[3], bool has_
       if constexpr (cx * cx + cy * cy + cz * cz == 1 || cx * cx + cy * cy + cz * cz == 2)
         Ap[lane] = fma(t, ds, Ap[lane]);  // the shear part ds is nonzero
     });
-    A = Ap[0] + Ap[1] + Ap[2];
-    B = Bp[0] + Bp[1] + Bp[2];
+    A = fma(rl[2], Ap[2], fma(rl[1], Ap[1], rl[0] * Ap[0]));
+    B = fma(rl[2], Bp[2], fma(rl[1], Bp[1], rl[0] * Bp[0]));
   }
   const T ib = rcp(beta);
   T gamma = T(2);
