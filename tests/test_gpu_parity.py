@@ -387,6 +387,36 @@ def test_channel_half_storage(elbm, storage, bound):
     assert err < bound
 
 
+# The 3-level sphere (inlet, outflow, drag) and the 4-level forest in 16-bit storage on
+# small grids, against the FP64 oracle from identical inputs: the error is the storage
+# quantisation of h over the horizon.  Measured on MI355X: sphere (20 steps) FP16s 8.3e-4
+# of U and 9.8e-5 of the drag, BF16s 7.1e-3 and 5.3e-4; forest (10 steps) FP16s 1.7e-4,
+# BF16s 1.8e-3.  Bounds about twice that.
+@pytest.mark.parametrize("storage,bound,dbound", [("f16s", 2e-3, 3e-4), ("bf16s", 1.5e-2, 2e-3)])
+def test_sphere_three_level_half_storage(elbm, storage, bound, dbound):
+    sp = synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)), l2=((16, 8, 8), (24, 16, 16)),
+                        centre=(20, 12, 12))
+    g, o = pair(elbm, sp, storage, 20)
+    err = max_du(g, o, sp)
+    print("sphere %s max|du|/U = %.3e" % (storage, err))
+    assert err < bound
+    Fg, sg = g.drag(2)
+    Fo, so = o.drag(2)
+    assert sg == so
+    derr = float(np.max(np.abs(Fg - Fo)) / np.max(np.abs(Fo)))
+    print("sphere %s drag relative error %.3e" % (storage, derr))
+    assert derr < dbound
+
+
+@pytest.mark.parametrize("storage,bound", [("f16s", 4e-4), ("bf16s", 4e-3)])
+def test_forest_four_level_half_storage(elbm, storage, bound):
+    sp = synth.forest3d(root=(4, 4, 4), counts=(8, 8, 1), block=8)
+    g, o = pair(elbm, sp, storage, 10)
+    err = max_du(g, o, sp)
+    print("forest %s max|du|/U = %.3e" % (storage, err))
+    assert err < bound
+
+
 @pytest.mark.parametrize("storage", ["f16s", "bf16s"])
 def test_half_storage_launch_configurations_bitwise_equal(elbm, storage):
     """16-bit storage has its own store policy and graph capture order: the cached kind of
