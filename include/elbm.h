@@ -241,9 +241,12 @@ elbm_status elbm_get_launch(const elbm_ctx *ctx, int32_t cfg[6]);
  * launch tuner (paper_1608_06915_amd/tune.py, every candidate timed in a process of its
  * own); `steps` is reserved and ignored. */
 elbm_status elbm_tune(elbm_ctx *ctx, const char *cache_path, int steps);
-/* Time `steps` coarse steps with HIP events around every stream-collide launch;
- * returns the total and summed stream-collide milliseconds and launch count.
- * Synchronous. */
+/* Advance `steps` coarse steps eagerly (no graphs), timing every tick's stream-collide
+ * with HIP events on the bound stream: a tick of one launch passes the events to
+ * hipExtLaunchKernel, which stamps them with the kernel's own start and end; a tick split
+ * into two launches (pipeline modes) records them around both.  Returns the total
+ * milliseconds, the summed stream-collide milliseconds and the number of timed ticks;
+ * the state advances exactly as elbm_advance would.  Synchronous. */
 elbm_status elbm_profile(elbm_ctx *ctx, int steps, double *ms_total, double *ms_stream_collide,
                          int64_t *n_launches);
 /* Measurement aid, not part of the method: a plain streaming copy of `bytes` (a

@@ -1311,9 +1311,10 @@ elbm_status enqueue_tick_io(elbm_ctx *c, int t, void *const src[MAXL], void *con
     HIPCK(c, hipEventCreate(&e1));
     c->tev.push_back(e0);
     c->tev.push_back(e1);
-    if (!split) {
+    if (!split && s.n_items > 0) {
       // one launch: its dispatch packet stamps the events with the kernel's own start
-      // and end, as a kernel tracer reports it
+      // and end, as a kernel tracer reports it (a tick without items launches nothing,
+      // and its events are recorded below, back to back)
       cfg.ev0 = e0;
       cfg.ev1 = e1;
       elbm_status st = run();
