@@ -929,12 +929,17 @@ size_t store_bytes(int st);
 // bricks' populations (read + write, ~14.5 ns per 3-D FP32 brick); gather + coupling
 // take ~10 us plus ~20 ns per coupling workgroup plus ~0.25 ns per interpolation
 // point.  (Two-level channel, FP32: 82 us estimated against 58 us, measured 77 and
-// 55 us; with 16-bit storage, and on the four-level forest's ticks, the coupling
-// branch is the longer one.)
+// 55 us; on the four-level forest's ticks the coupling branch is the longer one.)
+// With 16-bit storage the stream-collide is bound by its arithmetic, not its bytes, and
+// the coupling kernels share its SIMDs: there the coupling branch is the longer one in
+// every coupling tick measured (the three-level sphere's level 0-2 tick: ~190 us of
+// gather + coupling beside a 158 us stream-collide), so it is always captured first.
 bool coupling_longer(const elbm_ctx *c, const Tick &tk) {
+  if (tk.tile_n + tk.ring_n == 0) return false;
+  if (store_bytes(c->storage) == 2) return true;
   const double sc_ns = (double)tk.sc_n * BN * c->Q * 2.0 * (double)store_bytes(c->storage) / 3800.0;
   const double cp_ns = 10000.0 + 20.0 * (double)(tk.tile_n + (tk.ring_n + 255) / 256) + 0.25 * (double)tk.gp_n;
-  return tk.tile_n + tk.ring_n > 0 && cp_ns > sc_ns;
+  return cp_ns > sc_ns;
 }
 
 void build_schedule(elbm_ctx *c) {
