@@ -125,8 +125,8 @@ def test_launch_cache_entries_name_the_benchmark_shapes(elbm):
                 assert m, "unparsable cache line: %r" % line
                 entries[m.group(1)] = [int(v) for v in m.groups()[1:]]
     keys = set()
-    for sp, storages in ((synth.channel3d(), ("f32", "f16s")), (synth.sphere3d(), ("f32", "f16s")),
-                         (synth.forest3d(), ("f32", "f16s")), (synth.cylinder2d(), ("f32",))):
+    for sp, storages in ((synth.channel3d(), ("f32", "f16s", "bf16s")), (synth.sphere3d(), ("f32", "f16s", "bf16s")),
+                         (synth.forest3d(), ("f32", "f16s", "bf16s")), (synth.cylinder2d(), ("f32",))):
         g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, "f32")
         synth.apply(sp, g)
         shape = "".join("_%d" % g.level_info(l)[3] for l in range(sp.levels))  # bricks do not depend on storage
