@@ -251,6 +251,47 @@ def test_launch_configurations_bitwise_equal(elbm, launch):
         assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True)
 
 
+def _lattice(elbm, sp, storage, launch):
+    print("case %s storage=%s launch=%s" % (sp.name, storage, launch), flush=True)
+    g = elbm.Lattice(sp.D, sp.N, sp.periodic, sp.nu0, sp.levels, storage)
+    synth.apply(sp, g)
+    g.bind()
+    g.set_launch(**launch)
+    g.set_gamma_output(True)
+    for l in range(sp.levels):
+        lo, n = g.level_box(l)
+        rho, u, nz = sp.init(l, lo, n)
+        g.init(l, rho, u, nz)
+    return g
+
+
+@pytest.mark.parametrize("case", ["sphere-f32", "sphere-f16s", "forest-f32", "forest-bf16s", "channel-f16s"])
+def test_graph_replays_bitwise_equal_to_eager(elbm, case):
+    """Graph replays (the coupling of a tick on a parallel branch beside its
+    stream-collide, Sec. III.C) compute what the one-stream eager order computes:
+    populations, gamma and drag equal bit for bit over 13 coarse steps (a graph of ten
+    steps, then single-step graphs of both parities), on two to four levels and in 32-
+    and 16-bit storage."""
+    name, storage = case.split("-")
+    sp = {"sphere": lambda: synth.sphere3d(48, 24, 24, D_fine=6.0, l1=((12, 6, 6), (30, 18, 18)),
+                                           l2=((16, 8, 8), (24, 16, 16)), centre=(20, 12, 12), noise=1e-3),
+          "forest": lambda: synth.forest3d(root=(4, 4, 4), counts=(8, 8, 1), block=8),
+          "channel": lambda: synth.channel3d(32, 20, 16, 4, nu0=0.01)}[name]()
+    thr = 128 if storage != "f32" else 256
+    g0 = _lattice(elbm, sp, storage, dict(use_graph=0, threads=thr))
+    g1 = _lattice(elbm, sp, storage, dict(use_graph=10, xcd_remap=8, threads=thr))
+    g0.advance(13)
+    g1.advance(13)
+    g0.synchronize()
+    g1.synchronize()
+    for l in range(sp.levels):
+        assert np.array_equal(g0.get_f(l), g1.get_f(l), equal_nan=True), "level %d" % l
+        assert np.array_equal(g0.moments(l, gamma=True)[2], g1.moments(l, gamma=True)[2], equal_nan=True)
+        F0, s0 = g0.drag(l)
+        F1, s1 = g1.drag(l)
+        assert s0 == s1 and np.array_equal(F0, F1)
+
+
 @pytest.mark.parametrize("launch", [dict(use_graph=10, wg_per_cu=0, xcd_remap=8, threads=256),
                                     dict(use_graph=1, wg_per_cu=0, xcd_remap=2, pipeline=2)],
                          ids=["one-launch-per-tick", "split-ticks"])
